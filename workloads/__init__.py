@@ -1,0 +1,221 @@
+"""Seeded synthetic inputs for the soft demapper and its oracle.
+
+This module is the only code shared by the GPU path and the FP64 oracle, and it
+holds none of the demapping arithmetic: it draws constellations (point table +
+binary labelling), transmitted point indices, unit-variance Gaussian noise and
+forms the AWGN channel output y = fl32(x + sigma * z).
+
+Conventions (the paper gives none of them; these are the readings used
+throughout the project):
+
+* Random numbers come from NumPy's PCG64 generator, as the paper's transmitter
+  does for its symbol sequences (Sec. 3, experimental setup).  Each purpose
+  draws from its own stream, derived with ``SeedSequence(BASE_SEED,
+  spawn_key=(config, purpose, ...))``.
+* Constellations are normalised to unit energy per two real dimensions, so
+  E||x||^2 = D/2.  The SNR is Es(2D)/N0 with N0 = 2 sigma^2, hence
+  sigma^2 = 1 / (2 * 10^(SNR_dB/10)) for every dimensionality D.
+* A constellation is given as the paper's receiver receives it (Sec. 2): an
+  arbitrary point table and its bit mapping, uploaded as-is.  Rows need not be
+  in label order; the labelling is a bijection onto [0, M).
+* One noise draw z is shared by all SNR points of a configuration (common
+  random numbers); y_s = fl32(x_tx + sigma_s * z) with the product and the sum
+  each rounded in FP64 (no fused multiply-add), then rounded once to FP32.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+BASE_SEED = 210807004
+
+_PURPOSES = {
+    "constellation": 0,
+    "tx": 1,
+    "noise": 2,
+    "snr": 3,
+    "instances": 4,
+    "mlp_init": 5,
+    "mlp_train": 6,
+    "mlp_eval": 7,
+    "misc": 8,
+}
+
+
+def rng(config: int, purpose: str, *extra: int) -> np.random.Generator:
+    """PCG64 stream for (config, purpose, *extra) under the project base seed."""
+    key = (int(config), _PURPOSES[purpose]) + tuple(int(e) for e in extra)
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(BASE_SEED, spawn_key=key)))
+
+
+def sigma2_from_snr_db(snr_db) -> np.ndarray:
+    """Noise variance per real dimension for unit energy per 2D: 1/(2*10^(SNR/10))."""
+    s = np.asarray(snr_db, dtype=np.float64)
+    return 1.0 / (2.0 * np.power(10.0, s / 10.0))
+
+
+@dataclass(frozen=True)
+class Constellation:
+    """Point table (M x D, float32, arbitrary row order) and labels (M, uint16)."""
+
+    points: np.ndarray
+    labels: np.ndarray
+    name: str = ""
+
+    @property
+    def M(self) -> int:
+        return int(self.points.shape[0])
+
+    @property
+    def D(self) -> int:
+        return int(self.points.shape[1])
+
+    @property
+    def m(self) -> int:
+        return int(round(math.log2(self.M)))
+
+
+def _gray(i: np.ndarray) -> np.ndarray:
+    return i ^ (i >> 1)
+
+
+def pam_brgc(levels: int) -> tuple[np.ndarray, np.ndarray]:
+    """Equally spaced PAM amplitudes (ascending, unnormalised odd integers) and their BRGC labels."""
+    idx = np.arange(levels, dtype=np.int64)
+    amps = (2 * idx - (levels - 1)).astype(np.float64)
+    return amps, _gray(idx)
+
+
+def product_pam(levels: int, D: int, name: str) -> Constellation:
+    """D-fold product of a BRGC-labelled PAM, unit energy per 2D.
+
+    Row r enumerates amplitude indices (a_0, ..., a_{D-1}) in ascending
+    lexicographic order of the amplitudes; the label concatenates the per-
+    dimension BRGC labels with dimension 0 in the most significant position.
+    """
+    amps, glab = pam_brgc(levels)
+    q = int(round(math.log2(levels)))
+    scale = math.sqrt(1.0 / (2.0 * float(np.mean(amps * amps))))  # E x_d^2 = 1/2
+    grids = np.stack(np.meshgrid(*([np.arange(levels)] * D), indexing="ij"), axis=-1).reshape(-1, D)
+    pts = (amps[grids] * scale).astype(np.float32)
+    lab = np.zeros(grids.shape[0], dtype=np.int64)
+    for d in range(D):
+        lab = (lab << q) | glab[grids[:, d]]
+    return Constellation(pts, lab.astype(np.uint16), name)
+
+
+def dp_qpsk() -> Constellation:
+    """DP-QPSK: 4D, M=16, per-quadrature BRGC (bit 0 -> -A, 1 -> +A, A=1/sqrt2)."""
+    return product_pam(2, 4, "dp-qpsk")
+
+
+def dp_16qam() -> Constellation:
+    """Product of two Gray 16QAM: 4D, M=256, per-dimension 4-PAM with BRGC {00,01,11,10}."""
+    return product_pam(4, 4, "dp-16qam")
+
+
+def pam(levels: int) -> Constellation:
+    """1D BRGC PAM (used by closed-form checks)."""
+    return product_pam(levels, 1, f"{levels}-pam")
+
+
+def gaussian_constellation(M: int, D: int, config: int, *extra: int) -> Constellation:
+    """Random constellation: i.i.d. N(0,1) points rescaled to unit energy per 2D; label j = j."""
+    g = rng(config, "constellation", *extra)
+    X = g.standard_normal((M, D))
+    X *= math.sqrt((D / 2.0) / float(np.mean(np.sum(X * X, axis=1))))
+    return Constellation(X.astype(np.float32), np.arange(M, dtype=np.uint16), f"gauss-{D}d-{M}")
+
+
+def tx_indices(M: int, N: int, config: int, *extra: int) -> np.ndarray:
+    """Transmitted point (row) indices, uniform i.i.d. on [0, M)."""
+    return rng(config, "tx", *extra).integers(0, M, size=N, dtype=np.int64).astype(np.uint16)
+
+
+def unit_noise(N: int, D: int, config: int, *extra: int) -> np.ndarray:
+    """Unit-variance real Gaussian noise, FP64, N x D (shared by all SNR points)."""
+    return rng(config, "noise", *extra).standard_normal((N, D))
+
+
+def awgn(points: np.ndarray, tx: np.ndarray, z: np.ndarray, sigma2: float) -> np.ndarray:
+    """Channel output fl32(x_tx + sigma*z): FP64 product, FP64 sum, one FP32 rounding."""
+    x = points.astype(np.float64)[tx.astype(np.int64)]
+    s = math.sqrt(float(sigma2))
+    return (x + s * z).astype(np.float32)
+
+
+# --------------------------------------------------------------------------------------------
+# Workload recipes (sizes and SNR grids of the measured configurations)
+# --------------------------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    config: int
+    const: Constellation
+    N: int
+    snr_db: np.ndarray
+
+    @property
+    def sigma2(self) -> np.ndarray:
+        return sigma2_from_snr_db(self.snr_db)
+
+
+def workload(name: str, N: int | None = None) -> Workload:
+    """Named workloads; ``N`` overrides the symbol count (a prefix of the same streams)."""
+    if name == "dpqpsk":
+        c, n, snr, cfg = dp_qpsk(), 65536, np.arange(0, 11, 2, dtype=np.float64), 0
+    elif name == "dp16qam":
+        c, n, snr, cfg = dp_16qam(), 1 << 22, np.arange(0, 21, 2, dtype=np.float64), 1
+    elif name == "gauss8d2048":
+        c, n, snr, cfg = gaussian_constellation(2048, 8, 2), 1 << 24, np.arange(0, 16, 1, dtype=np.float64), 2
+    else:
+        raise KeyError(name)
+    return Workload(name, cfg, c, int(n if N is None else N), snr)
+
+
+def workload_tx_noise(w: Workload) -> tuple[np.ndarray, np.ndarray]:
+    """tx indices and unit noise of a workload; a smaller N is a prefix of the full draw."""
+    full = {"dpqpsk": 65536, "dp16qam": 1 << 22, "gauss8d2048": 1 << 24}[w.name]
+    if w.N > full:
+        raise ValueError("N larger than the workload's full size")
+    # Draw in fixed-size chunks so any prefix is reproducible without drawing the whole block.
+    tx = _chunked_tx(w.const.M, w.N, w.config)
+    z = _chunked_noise(w.N, w.const.D, w.config)
+    return tx, z
+
+
+_CHUNK = 1 << 16
+
+
+def _chunked_tx(M: int, N: int, config: int) -> np.ndarray:
+    out = np.empty(N, dtype=np.uint16)
+    for c0 in range(0, N, _CHUNK):
+        c1 = min(N, c0 + _CHUNK)
+        out[c0:c1] = tx_indices(M, _CHUNK, config, c0 // _CHUNK)[: c1 - c0]
+    return out
+
+
+def _chunked_noise(N: int, D: int, config: int) -> np.ndarray:
+    out = np.empty((N, D), dtype=np.float64)
+    for c0 in range(0, N, _CHUNK):
+        c1 = min(N, c0 + _CHUNK)
+        out[c0:c1] = unit_noise(_CHUNK, D, config, c0 // _CHUNK)[: c1 - c0]
+    return out
+
+
+def chunk_tx_noise(M: int, D: int, config: int, first: int, count: int) -> tuple[np.ndarray, np.ndarray]:
+    """tx and z for symbols [first, first+count) of a chunked workload stream."""
+    tx = np.empty(count, dtype=np.uint16)
+    z = np.empty((count, D), dtype=np.float64)
+    pos = 0
+    while pos < count:
+        n = first + pos
+        ci, off = divmod(n, _CHUNK)
+        take = min(_CHUNK - off, count - pos)
+        tx[pos:pos + take] = tx_indices(M, _CHUNK, config, ci)[off:off + take]
+        z[pos:pos + take] = unit_noise(_CHUNK, D, config, ci)[off:off + take]
+        pos += take
+    return tx, z
