@@ -1,0 +1,120 @@
+/*
+ * demap.h — C ABI of the MI355X soft-demapping library (libdemap.so, gfx950).
+ *
+ * The library computes, for a D-dimensional M-point constellation with a binary
+ * labelling, received symbols y over AWGN with per-dimension noise variance sigma2:
+ *
+ *   lambda_k(y) = ln sum_{x in X_k^1} exp(-||y-x||^2/(2 sigma2))
+ *               - ln sum_{x in X_k^0} exp(-||y-x||^2/(2 sigma2)),     k = 0 .. m-1,
+ *
+ * where X_k^b holds the points whose label has bit k equal to b, bit k being label
+ * bit (m-1-k) (most significant first), and the Monte-Carlo GMI / MI estimates
+ *
+ *   GMI = (1/N) sum_n sum_k [1 - log2(1 + exp((1 - 2 b_{n,k}) lambda_{n,k}))]
+ *   MI  = (1/N) sum_n [log2 M - log2 sum_j exp(-(||y_n-x_j||^2 - ||y_n-x_{s_n}||^2)/(2 sigma2))]
+ *
+ * in bits per D-dimensional symbol.  The paper's receiver takes an arbitrary,
+ * non-symmetric point table and bit mapping uploaded to the GPU (Sec. 2) and its
+ * geometric-shaping search scores constellations by the AWGN GMI (Sec. 5); it gives
+ * no formula, so the standard bit-metric-decoding definitions above are used.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a status code (DM_OK or a negative DM_E*), never throws, and
+ *    stores a message retrievable with dm_last_error() on the calling thread.
+ *  - Data buffers (y, tx, llr) are DEVICE pointers owned by the caller.  Small
+ *    results (gmi, mi) are HOST pointers.  Constellations are uploaded from HOST
+ *    arrays and owned by the library until destroyed.
+ *  - All GPU work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
+ *    stream).  Calls that return host results synchronise that stream before
+ *    returning.  Calls sharing one constellation or plan on different streams at
+ *    the same time are not supported (they share library scratch).
+ *  - Layouts are row-major: points M x D, y N x D (FP32), llr N x m (FP32, nats).
+ *  - Limits: M = 2^m with 1 <= m <= 16, 1 <= D <= 32, 0 <= N < 2^31 per block.
+ */
+#ifndef DEMAP_H
+#define DEMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DM_OK = 0,
+    DM_EINVAL = -1,       /* a null required pointer, bad size, sigma2 <= 0 or not finite,
+                             labels not a bijection onto [0, M), M not a power of two */
+    DM_EUNSUPPORTED = -2, /* m > 16, D > 32, or the precision is not available for this shape */
+    DM_EHIP = -3,         /* a HIP runtime call failed; dm_last_error() names it */
+    DM_ENOMEM = -4        /* device or host allocation failed */
+};
+
+/* Arithmetic of the distance term (the log-sum-exp always runs in FP32). */
+enum {
+    DM_PREC_FP32 = 0,    /* direct differences ||y-x||^2 on the vector ALU, FP32 */
+    DM_PREC_BF16 = 1,    /* cross term 2y.x - ||x||^2 on MFMA, BF16 operands, FP32 accumulate */
+    DM_PREC_FP16 = 2,    /* as BF16 with FP16 operands */
+    DM_PREC_BF16X3 = 3,  /* BF16 hi/lo split operands, three products per term (~16-bit operands) */
+    DM_PREC_FP16X3 = 4   /* FP16 hi/lo split operands, three products per term (~22-bit operands) */
+};
+
+typedef struct dm_constellation dm_constellation;
+
+/*
+ * Upload a constellation (the paper's uploaded point table + bit mapping, Sec. 2).
+ *   points  HOST, M x D FP32 row-major, any row order.
+ *   labels  HOST, M uint16, a bijection onto [0, M); row j carries label labels[j].
+ * The library validates, reorders the table into label order, derives the MFMA
+ * operand tables and uploads them to the current device.  *out is owned by the
+ * caller and released with dm_constellation_destroy.
+ * Errors: DM_EINVAL (null pointer, M not 2^m, labels not a bijection, non-finite
+ * point), DM_EUNSUPPORTED (m > 16 or D > 32), DM_ENOMEM, DM_EHIP.
+ */
+int dm_constellation_create(const float* points, const uint16_t* labels, int32_t M, int32_t D,
+                            dm_constellation** out);
+void dm_constellation_destroy(dm_constellation* c);
+
+/*
+ * Exact bit-wise LLRs of one received block (the log-sum-exp LLRs of the header).
+ *   y       DEVICE, N x D FP32.       llr  DEVICE, N x m FP32 output (nats).
+ *   sigma2  noise variance per real dimension, > 0.
+ *   prec    DM_PREC_*.
+ * Enqueued on `stream`; does not synchronise.  N == 0 is a no-op.
+ * Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_EHIP, DM_ENOMEM.
+ */
+int dm_demap_llr(const dm_constellation* c, double sigma2, const float* y, int64_t N, float* llr,
+                 int prec, void* stream);
+
+/*
+ * Monte-Carlo GMI (and MI) at n_snr noise levels over the same transmitted block
+ * (the AWGN GMI the paper's shaping search evaluates, Sec. 5).
+ *   sigma2  HOST, n_snr noise variances.
+ *   y       HOST array of n_snr DEVICE pointers, each N x D FP32 (received block s).
+ *   tx      DEVICE, N uint16 transmitted ROW indices into the uploaded point table.
+ *   llr     HOST array of n_snr DEVICE pointers (N x m FP32 each) or NULL for none.
+ *   gmi     HOST, n_snr FP64 outputs (bits per symbol; NaN when N == 0).
+ *   mi      HOST, n_snr FP64 outputs or NULL.
+ * Synchronises `stream` before returning.  The result is bit-reproducible for a
+ * given input and precision (fixed-point accumulation across the grid).
+ * Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_EHIP, DM_ENOMEM.
+ */
+int dm_gmi_estimate(const dm_constellation* c, int n_snr, const double* sigma2,
+                    const float* const* y, const uint16_t* tx, int64_t N, float* const* llr,
+                    double* gmi, double* mi, int prec, void* stream);
+
+/* Number of (symbol, bit) pairs that the last call on this thread sent through the
+ * far-subset underflow fix-up, per SNR point (HOST array of n_snr, may be NULL).
+ * Returns the total, or a negative DM_E* if no call has run on this thread. */
+int64_t dm_last_fixup_count(int64_t* per_snr, int n_snr);
+
+/* Thread-local description of the last error on the calling thread ("" if none). */
+const char* dm_last_error(void);
+
+/* Library version string. */
+const char* dm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMAP_H */

@@ -1,0 +1,168 @@
+"""MI355X soft demapper: exact bit-wise LLRs and Monte-Carlo GMI/MI (HIP, gfx950).
+
+Thin ctypes binding over ``libdemap.so`` (C ABI declared in ``include/demap.h``).
+Every computation runs in the library's HIP kernels; this module only checks and
+marshals arguments.  PyTorch supplies device memory and the current stream.
+If the library is not built the functions raise: there is no CPU fallback.
+
+Python names follow the C entry points without their ``dm_`` prefix:
+``demap_llr`` -> ``dm_demap_llr``, ``gmi_estimate`` -> ``dm_gmi_estimate``, ...
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+from typing import Sequence
+
+import numpy as np
+
+__all__ = ["Constellation", "DemapError", "PREC", "demap_llr", "gmi_estimate", "last_fixup_count",
+           "library_path", "load_library"]
+
+_LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}
+_ERRORS = {-1: "DM_EINVAL", -2: "DM_EUNSUPPORTED", -3: "DM_EHIP", -4: "DM_ENOMEM"}
+
+_lib = None
+
+
+class DemapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library_path() -> Path:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libdemap.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not _LIB_PATH.exists():
+        raise RuntimeError(f"{_LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    lib.dm_constellation_create.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.dm_constellation_create.restype = I
+    lib.dm_constellation_destroy.argtypes = [P]
+    lib.dm_constellation_destroy.restype = None
+    lib.dm_demap_llr.argtypes = [P, D, P, I64, P, I, P]
+    lib.dm_demap_llr.restype = I
+    lib.dm_gmi_estimate.argtypes = [P, I, P, P, P, I64, P, P, P, I, P]
+    lib.dm_gmi_estimate.restype = I
+    lib.dm_last_fixup_count.argtypes = [P, I]
+    lib.dm_last_fixup_count.restype = I64
+    lib.dm_last_error.restype = ctypes.c_char_p
+    lib.dm_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise DemapError(rc, load_library().dm_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t, dtype_names, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if str(t.dtype).replace("torch.", "") not in dtype_names:
+        raise TypeError(f"{name} must have dtype in {dtype_names}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Constellation:
+    """A point table (M x D) and bit mapping uploaded to the current GPU."""
+
+    def __init__(self, points, labels):
+        lib = load_library()
+        pts = np.ascontiguousarray(points, dtype=np.float32)
+        lab = np.ascontiguousarray(labels, dtype=np.uint16)
+        if pts.ndim != 2 or lab.shape != (pts.shape[0],):
+            raise ValueError("points must be M x D and labels length M")
+        self.M, self.D = int(pts.shape[0]), int(pts.shape[1])
+        self.m = self.M.bit_length() - 1
+        h = ctypes.c_void_p()
+        _check(lib.dm_constellation_create(pts.ctypes.data_as(ctypes.c_void_p), lab.ctypes.data_as(ctypes.c_void_p),
+                                           self.M, self.D, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().dm_constellation_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def demap_llr(const: Constellation, sigma2: float, y, llr=None, prec: str = "fp32", stream=None):
+    """Exact LLRs (nats, N x m FP32) of the received block y (N x D FP32 on the GPU)."""
+    import torch
+    N = int(y.shape[0])
+    yp = _dev_tensor(y, ("float32",), (N, const.D), "y")
+    if llr is None:
+        llr = torch.empty((N, const.m), dtype=torch.float32, device=y.device)
+    lp = _dev_tensor(llr, ("float32",), (N, const.m), "llr")
+    _check(load_library().dm_demap_llr(const.handle, float(sigma2), yp, N, lp, PREC[prec], _stream_handle(stream)))
+    return llr
+
+
+def gmi_estimate(const: Constellation, sigma2: Sequence[float], ys, tx, llrs=None, prec: str = "fp32",
+                 stream=None, want_mi: bool = True):
+    """Monte-Carlo GMI (and MI) in bits/symbol at each noise variance.
+
+    ys: list of n_snr tensors (N x D FP32) or one (n_snr, N, D) tensor.
+    tx: (N,) int16/uint16 tensor of transmitted row indices.
+    llrs: None, or a list / (n_snr, N, m) tensor receiving the LLRs.
+    Returns (gmi, mi) as float64 NumPy arrays (mi is None if want_mi is False).
+    """
+    s2 = np.ascontiguousarray(np.asarray(sigma2, dtype=np.float64).reshape(-1))
+    ns = int(s2.shape[0])
+    ylist = [ys[i] for i in range(ns)]
+    if len(ylist) != ns:
+        raise ValueError("need one received block per SNR point")
+    N = int(ylist[0].shape[0])
+    yptr = (ctypes.c_void_p * ns)(*[_dev_tensor(t, ("float32",), (N, const.D), "y[s]").value for t in ylist])
+    txp = _dev_tensor(tx, ("int16", "uint16"), (N,), "tx")
+    lptr = None
+    if llrs is not None:
+        llist = [llrs[i] for i in range(ns)]
+        lptr = (ctypes.c_void_p * ns)(*[_dev_tensor(t, ("float32",), (N, const.m), "llr[s]").value for t in llist])
+    gmi = np.empty(ns, dtype=np.float64)
+    mi = np.empty(ns, dtype=np.float64) if want_mi else None
+    _check(load_library().dm_gmi_estimate(
+        const.handle, ns, s2.ctypes.data_as(ctypes.c_void_p), ctypes.cast(yptr, ctypes.c_void_p), txp, N,
+        None if lptr is None else ctypes.cast(lptr, ctypes.c_void_p), gmi.ctypes.data_as(ctypes.c_void_p),
+        None if mi is None else mi.ctypes.data_as(ctypes.c_void_p), PREC[prec], _stream_handle(stream)))
+    return gmi, mi
+
+
+def last_fixup_count(n_snr: int):
+    """(total, per-SNR) (symbol, bit) pairs the last gmi_estimate on this thread sent to the fix-up."""
+    per = np.zeros(max(1, n_snr), dtype=np.int64)
+    tot = load_library().dm_last_fixup_count(per.ctypes.data_as(ctypes.c_void_p), n_snr)
+    if tot < 0:
+        _check(int(tot))
+    return int(tot), per[:n_snr]

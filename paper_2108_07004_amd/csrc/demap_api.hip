@@ -1,0 +1,326 @@
+// C ABI of the soft-demapping library: validation, constellation upload (label-order
+// table), library scratch, kernel launches and the fixed-point GMI / MI finalisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/demap.h"
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+using dm::FixEntry;
+using dm::LaunchArgs;
+
+struct dm_constellation {
+    int M = 0, D = 0, m = 0, DP = 0, device = 0, cus = 0;
+    float* d_table = nullptr;          // M x DP FP32, label order, zero-padded columns
+    uint16_t* d_row2label = nullptr;   // M
+    std::vector<float> h_table;        // host copy of the label-order table (M x D)
+    // scratch (grow-only), shared by calls on this constellation
+    unsigned long long* d_acc = nullptr;  // kMaxSnrPerLaunch x kAccSlots x 2
+    uint32_t* d_fix_pairs = nullptr;      // kMaxSnrPerLaunch + 1 (last word: bad-tx flag)
+    uint32_t* d_queue_count = nullptr;
+    FixEntry* d_queue = nullptr;
+    uint32_t queue_cap = 0;
+    void* h_stage = nullptr;              // pinned: acc + fix_pairs
+    std::mutex mu;
+};
+
+namespace {
+
+thread_local std::string g_err;
+thread_local std::vector<int64_t> g_fix_counts;
+thread_local bool g_have_fix = false;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(DM_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return hip_fail(_e, #expr); \
+    } while (0)
+
+constexpr size_t kStageBytes =
+    sizeof(unsigned long long) * dm::kMaxSnrPerLaunch * dm::kAccSlots * 2 + sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1);
+
+// Device pointers must be device (or managed) memory of the current device.
+int check_device_ptr(const void* p, const char* name, int device) {
+    if (!p) return fail(DM_EINVAL, "%s is null", name);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DM_EINVAL, "%s is not a device pointer", name);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(DM_EINVAL, "%s is not device memory", name);
+    if (attr.device != device) return fail(DM_EINVAL, "%s lives on device %d, constellation on %d", name, attr.device, device);
+    return DM_OK;
+}
+
+int check_current_device(const dm_constellation* c) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device) return fail(DM_EINVAL, "current device %d differs from the constellation's device %d", dev, c->device);
+    return DM_OK;
+}
+
+int ensure_scratch(dm_constellation* c, uint64_t want_queue) {
+    if (!c->d_acc) {
+        HIP_TRY(hipMalloc(&c->d_acc, sizeof(unsigned long long) * dm::kMaxSnrPerLaunch * dm::kAccSlots * 2));
+        HIP_TRY(hipMalloc(&c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1)));
+        HIP_TRY(hipMalloc(&c->d_queue_count, sizeof(uint32_t)));
+        HIP_TRY(hipHostMalloc(&c->h_stage, kStageBytes, hipHostMallocDefault));
+    }
+    const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(want_queue, 1024), 1u << 22);
+    if (cap > c->queue_cap) {
+        if (c->d_queue) HIP_TRY(hipFree(c->d_queue));
+        c->d_queue = nullptr;
+        c->queue_cap = 0;
+        if (hipMalloc(&c->d_queue, sizeof(FixEntry) * cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DM_ENOMEM, "fix-up queue allocation (%llu entries) failed", (unsigned long long)cap);
+        }
+        c->queue_cap = (uint32_t)cap;
+    }
+    return DM_OK;
+}
+
+int persistent_grid(const dm_constellation* c, int64_t tiles, int blocks_per_cu) {
+    const int64_t g = (int64_t)c->cus * blocks_per_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, g));
+}
+
+LaunchArgs base_args(const dm_constellation* c, int64_t N) {
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.table = c->d_table;
+    a.row2label = c->d_row2label;
+    a.N = N;
+    a.M = c->M;
+    a.D = c->D;
+    a.m = c->m;
+    a.K = (float)(123 - c->m);
+    a.flag_thresh = std::ldexp(1.0f, c->m - 102);
+    a.near_thresh = std::ldexp(1.0f, c->m - 42);
+    a.queue = c->d_queue;
+    a.queue_count = c->d_queue_count;
+    a.queue_cap = c->queue_cap;
+    return a;
+}
+
+float exponent_scale(double sigma2) { return (float)(1.4426950408889634 / (2.0 * sigma2)); }
+
+int validate_sigma2(double s2) {
+    if (!(s2 > 0.0) || !std::isfinite(s2)) return fail(DM_EINVAL, "sigma2 must be finite and > 0 (got %g)", s2);
+    const double c = 1.4426950408889634 / (2.0 * s2);
+    if (!(c < 1e30) || !(c > 1e-30)) return fail(DM_EUNSUPPORTED, "sigma2 %g is outside the supported range", s2);
+    return DM_OK;
+}
+
+// Run the demapper over up to kMaxSnrPerLaunch SNR points of one block.
+int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
+              int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st) {
+    if (prec != DM_PREC_FP32) return fail(DM_EUNSUPPORTED, "precision %d is not available yet", prec);
+    const int tile = dm::valu_tile_symbols();
+    const int64_t tiles_per_snr = (N + tile - 1) / tile;
+    int r = ensure_scratch(c, (uint64_t)N * n_snr);
+    if (r) return r;
+    LaunchArgs a = base_args(c, N);
+    a.tx = tx;
+    a.tiles_per_snr = tiles_per_snr;
+    a.n_snr = n_snr;
+    a.want_llr = llr ? 1 : 0;
+    a.acc = want_acc ? c->d_acc : nullptr;
+    a.fix_pairs = want_acc ? c->d_fix_pairs : nullptr;
+    a.bad_tx = want_acc ? c->d_fix_pairs + dm::kMaxSnrPerLaunch : nullptr;
+    for (int s = 0; s < n_snr; ++s) {
+        a.snr[s].y = y[s];
+        a.snr[s].llr = llr ? llr[s] : nullptr;
+        a.snr[s].c = exponent_scale(sigma2[s]);
+    }
+    if (want_acc) {
+        HIP_TRY(hipMemsetAsync(c->d_acc, 0, sizeof(unsigned long long) * n_snr * dm::kAccSlots * 2, st));
+        HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
+    }
+    HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
+    const int grid = persistent_grid(c, tiles_per_snr * n_snr, 2);
+    const int fix_grid = c->cus * 4;
+    HIP_TRY(dm::launch_demap_valu(a, grid, fix_grid, st));
+    return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dm_last_error(void) { return g_err.c_str(); }
+
+const char* dm_version(void) { return "demap-mi355x 0.1 (gfx950)"; }
+
+int dm_constellation_create(const float* points, const uint16_t* labels, int32_t M, int32_t D,
+                            dm_constellation** out) {
+    g_err.clear();
+    if (!points || !labels || !out) return fail(DM_EINVAL, "null argument");
+    *out = nullptr;
+    if (M < 2 || (M & (M - 1))) return fail(DM_EINVAL, "M=%d is not a power of two >= 2", M);
+    int m = 0;
+    while ((1 << m) < M) ++m;
+    if (m > 16) return fail(DM_EUNSUPPORTED, "m=%d > 16", m);
+    if (D < 1) return fail(DM_EINVAL, "D=%d < 1", D);
+    if (D > 32) return fail(DM_EUNSUPPORTED, "D=%d > 32", D);
+    std::vector<int> row_of(M, -1);
+    for (int j = 0; j < M; ++j) {
+        if (labels[j] >= (uint32_t)M || row_of[labels[j]] >= 0)
+            return fail(DM_EINVAL, "labels are not a bijection onto [0, M) (row %d)", j);
+        row_of[labels[j]] = j;
+    }
+    for (size_t i = 0; i < (size_t)M * D; ++i)
+        if (!std::isfinite(points[i]) || std::fabs(points[i]) > 1e15f)
+            return fail(DM_EINVAL, "point coordinate %zu is not finite or exceeds 1e15", i);
+
+    auto* c = new (std::nothrow) dm_constellation();
+    if (!c) return fail(DM_ENOMEM, "host allocation failed");
+    c->M = M;
+    c->D = D;
+    c->m = m;
+    c->DP = dm::padded_dim(D);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "device query");
+    }
+    c->h_table.assign((size_t)M * D, 0.0f);
+    std::vector<float> padded((size_t)M * c->DP, 0.0f);
+    std::vector<uint16_t> r2l(labels, labels + M);
+    for (int l = 0; l < M; ++l)
+        for (int d = 0; d < D; ++d) {
+            c->h_table[(size_t)l * D + d] = points[(size_t)row_of[l] * D + d];
+            padded[(size_t)l * c->DP + d] = points[(size_t)row_of[l] * D + d];
+        }
+    if ((e = hipMalloc(&c->d_table, padded.size() * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&c->d_row2label, M * sizeof(uint16_t))) != hipSuccess ||
+        (e = hipMemcpy(c->d_table, padded.data(), padded.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_row2label, r2l.data(), M * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess) {
+        dm_constellation_destroy(c);
+        return hip_fail(e, "constellation upload");
+    }
+    *out = c;
+    return DM_OK;
+}
+
+void dm_constellation_destroy(dm_constellation* c) {
+    if (!c) return;
+    (void)hipFree(c->d_table);
+    (void)hipFree(c->d_row2label);
+    (void)hipFree(c->d_acc);
+    (void)hipFree(c->d_fix_pairs);
+    (void)hipFree(c->d_queue_count);
+    (void)hipFree(c->d_queue);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    delete c;
+}
+
+int dm_demap_llr(const dm_constellation* cc, double sigma2, const float* y, int64_t N, float* llr, int prec,
+                 void* stream) {
+    g_err.clear();
+    auto* c = const_cast<dm_constellation*>(cc);
+    if (!c) return fail(DM_EINVAL, "constellation is null");
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(DM_EINVAL, "N=%lld out of range", (long long)N);
+    if (prec < DM_PREC_FP32 || prec > DM_PREC_FP16X3) return fail(DM_EINVAL, "unknown precision %d", prec);
+    int r = validate_sigma2(sigma2);
+    if (r) return r;
+    if (N == 0) return DM_OK;
+    if ((r = check_current_device(c))) return r;
+    if ((r = check_device_ptr(y, "y", c->device))) return r;
+    if ((r = check_device_ptr(llr, "llr", c->device))) return r;
+    std::lock_guard<std::mutex> lock(c->mu);
+    const float* ys[1] = {y};
+    float* ls[1] = {llr};
+    return run_chunk(c, 1, &sigma2, ys, nullptr, N, ls, false, prec, (hipStream_t)stream);
+}
+
+int dm_gmi_estimate(const dm_constellation* cc, int n_snr, const double* sigma2, const float* const* y,
+                    const uint16_t* tx, int64_t N, float* const* llr, double* gmi, double* mi, int prec,
+                    void* stream) {
+    g_err.clear();
+    auto* c = const_cast<dm_constellation*>(cc);
+    if (!c || !sigma2 || !y || !gmi) return fail(DM_EINVAL, "null argument");
+    if (n_snr < 1) return fail(DM_EINVAL, "n_snr=%d < 1", n_snr);
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(DM_EINVAL, "N=%lld out of range", (long long)N);
+    if (prec < DM_PREC_FP32 || prec > DM_PREC_FP16X3) return fail(DM_EINVAL, "unknown precision %d", prec);
+    int r;
+    for (int s = 0; s < n_snr; ++s)
+        if ((r = validate_sigma2(sigma2[s]))) return r;
+    g_fix_counts.assign(n_snr, 0);
+    g_have_fix = true;
+    if (N == 0) {
+        for (int s = 0; s < n_snr; ++s) {
+            gmi[s] = NAN;
+            if (mi) mi[s] = NAN;
+        }
+        return DM_OK;
+    }
+    if ((r = check_current_device(c))) return r;
+    if ((r = check_device_ptr(tx, "tx", c->device))) return r;
+    for (int s = 0; s < n_snr; ++s) {
+        if ((r = check_device_ptr(y[s], "y[s]", c->device))) return r;
+        if (llr && (r = check_device_ptr(llr[s], "llr[s]", c->device))) return r;
+    }
+    std::lock_guard<std::mutex> lock(c->mu);
+    hipStream_t st = (hipStream_t)stream;
+    for (int s0 = 0; s0 < n_snr; s0 += dm::kMaxSnrPerLaunch) {
+        const int ns = std::min(dm::kMaxSnrPerLaunch, n_snr - s0);
+        r = run_chunk(c, ns, sigma2 + s0, y + s0, tx, N, llr ? llr + s0 : nullptr, true, prec, st);
+        if (r) return r;
+        auto* acc = (unsigned long long*)c->h_stage;
+        auto* fix = (uint32_t*)(acc + (size_t)dm::kMaxSnrPerLaunch * dm::kAccSlots * 2);
+        HIP_TRY(hipMemcpyAsync(acc, c->d_acc, sizeof(unsigned long long) * ns * dm::kAccSlots * 2, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(fix, c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (fix[dm::kMaxSnrPerLaunch]) return fail(DM_EINVAL, "a transmitted index is >= M");
+        for (int s = 0; s < ns; ++s) {
+            long long gs = 0, ms = 0;  // two's-complement sums of the fixed-point slots
+            for (int k = 0; k < dm::kAccSlots; ++k) {
+                gs += (long long)acc[((size_t)s * dm::kAccSlots + k) * 2 + 0];
+                ms += (long long)acc[((size_t)s * dm::kAccSlots + k) * 2 + 1];
+            }
+            gmi[s0 + s] = (double)gs / dm::kFixScale / (double)N;
+            if (mi) mi[s0 + s] = (double)ms / dm::kFixScale / (double)N;
+            g_fix_counts[s0 + s] = fix[s];
+        }
+    }
+    return DM_OK;
+}
+
+int64_t dm_last_fixup_count(int64_t* per_snr, int n_snr) {
+    if (!g_have_fix) return DM_EINVAL;
+    int64_t total = 0;
+    for (size_t s = 0; s < g_fix_counts.size(); ++s) {
+        total += g_fix_counts[s];
+        if (per_snr && (int)s < n_snr) per_snr[s] = g_fix_counts[s];
+    }
+    return total;
+}
+
+}  // extern "C"

@@ -219,3 +219,16 @@ def chunk_tx_noise(M: int, D: int, config: int, first: int, count: int) -> tuple
         z[pos:pos + take] = unit_noise(_CHUNK, D, config, ci)[off:off + take]
         pos += take
     return tx, z
+
+
+def awgn_torch(points, tx, z, sigma2):
+    """GPU twin of ``awgn``: same FP64 product and sum, one FP32 rounding (bit-identical).
+
+    points: (M, D) float32 array or tensor; tx: (N,) integer tensor; z: (N, D) float64 tensor.
+    """
+    import torch
+    dev = z.device
+    p64 = torch.as_tensor(np.asarray(points), dtype=torch.float32).to(dev).to(torch.float64)
+    x = p64[tx.to(torch.int64)]
+    s = math.sqrt(float(sigma2))
+    return (x + (z * s)).to(torch.float32)
