@@ -1,0 +1,43 @@
+/*
+ * demap_probe.h — measurement utilities of libdemap.so (not part of the demapping path).
+ *
+ * The exact demapper evaluates one exp2 per (symbol, point) pair, so its throughput bound
+ * is the GPU's transcendental issue rate together with the adds of the subset sums.  These
+ * calls measure those rates and time the library's own kernels with HIP events, so that a
+ * benchmark can report its achieved rate against a measured roofline.
+ */
+#ifndef DEMAP_PROBE_H
+#define DEMAP_PROBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * Measure vector-ALU rates on the current device, synchronously on `stream`.
+ *   rates[0]  exp2 evaluations per second (v_exp_f32, all CUs)
+ *   rates[1]  FP32 FMA lane-operations per second (non-packed)
+ *   rates[2]  (exp2 + 2 FP32 adds) steps per second, the demapper's inner step
+ *   rates[3]  number of compute units used
+ * Returns 0, -1 (null argument), -3 (HIP error) or -4 (allocation failed).
+ */
+int dm_probe_valu_rates(double* rates, void* stream);
+
+/*
+ * Kernel timing with HIP events recorded on the launch stream around the demapping
+ * kernel and around the fix-up kernel of every later dm_demap_llr / dm_gmi_estimate
+ * call on this thread.  dm_profile_enable(1) starts (and clears), 0 stops.
+ * dm_profile_read waits for the recorded events and returns the summed milliseconds of
+ * the demapping kernels (main_ms) and fix-up kernels (fixup_ms) and the launch count;
+ * reset != 0 clears the record.  Returns 0 or a negative DM_E* code.
+ */
+int dm_profile_enable(int on);
+int dm_profile_read(double* main_ms, double* fixup_ms, int64_t* launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMAP_PROBE_H */

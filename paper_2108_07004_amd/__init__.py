@@ -17,7 +17,7 @@ from typing import Sequence
 import numpy as np
 
 __all__ = ["Constellation", "DemapError", "PREC", "demap_llr", "gmi_estimate", "last_fixup_count",
-           "library_path", "load_library"]
+           "library_path", "load_library", "probe_valu_rates", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}
@@ -55,6 +55,12 @@ def load_library():
     lib.dm_gmi_estimate.restype = I
     lib.dm_last_fixup_count.argtypes = [P, I]
     lib.dm_last_fixup_count.restype = I64
+    lib.dm_probe_valu_rates.argtypes = [P, P]
+    lib.dm_probe_valu_rates.restype = I
+    lib.dm_profile_enable.argtypes = [I]
+    lib.dm_profile_enable.restype = I
+    lib.dm_profile_read.argtypes = [P, P, P, I]
+    lib.dm_profile_read.restype = I
     lib.dm_last_error.restype = ctypes.c_char_p
     lib.dm_version.restype = ctypes.c_char_p
     _lib = lib
@@ -166,3 +172,26 @@ def last_fixup_count(n_snr: int):
     if tot < 0:
         _check(int(tot))
     return int(tot), per[:n_snr]
+
+
+def probe_valu_rates(stream=None) -> dict:
+    """Measured exp2, FMA and (exp2 + 2 add) rates of the current GPU (dm_probe_valu_rates)."""
+    r = np.zeros(4, dtype=np.float64)
+    rc = load_library().dm_probe_valu_rates(r.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    if rc != 0:
+        raise DemapError(rc, "dm_probe_valu_rates failed")
+    return {"exp2_per_s": r[0], "fma_per_s": r[1], "exp2_add2_per_s": r[2], "cus": int(r[3])}
+
+
+def profile_enable(on: bool = True):
+    """Start (and clear) or stop HIP-event timing of the library's kernels on this thread."""
+    _check(load_library().dm_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = False):
+    """(main_ms, fixup_ms, launches) summed over the recorded launches (dm_profile_read)."""
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load_library().dm_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n), 1 if reset else 0))
+    return a.value, b.value, n.value

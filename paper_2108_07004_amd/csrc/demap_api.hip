@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/demap.h"
+#include "../../include/demap_probe.h"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -38,6 +39,25 @@ namespace {
 thread_local std::string g_err;
 thread_local std::vector<int64_t> g_fix_counts;
 thread_local bool g_have_fix = false;
+
+// Kernel timing (dm_profile_*): events recorded around each launch on its stream.
+struct ProfRec {
+    hipEvent_t e0, e1, e2;
+};
+thread_local bool g_prof_on = false;
+thread_local std::vector<ProfRec> g_prof;
+thread_local std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -165,7 +185,18 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
     HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
     const int grid = persistent_grid(c, tiles_per_snr * n_snr, 2);
     const int fix_grid = c->cus * 4;
-    HIP_TRY(dm::launch_demap_valu(a, grid, fix_grid, st));
+    ProfRec pr{nullptr, nullptr, nullptr};
+    if (g_prof_on) {
+        pr = ProfRec{prof_event(), prof_event(), prof_event()};
+        if (pr.e0) HIP_TRY(hipEventRecord(pr.e0, st));
+    }
+    HIP_TRY(dm::launch_demap_valu(a, grid, st));
+    if (pr.e1) HIP_TRY(hipEventRecord(pr.e1, st));
+    HIP_TRY(dm::launch_fixup(a, fix_grid, st));
+    if (pr.e2) {
+        HIP_TRY(hipEventRecord(pr.e2, st));
+        g_prof.push_back(pr);
+    }
     return DM_OK;
 }
 
@@ -309,6 +340,44 @@ int dm_gmi_estimate(const dm_constellation* cc, int n_snr, const double* sigma2,
             if (mi) mi[s0 + s] = (double)ms / dm::kFixScale / (double)N;
             g_fix_counts[s0 + s] = fix[s];
         }
+    }
+    return DM_OK;
+}
+
+int dm_profile_enable(int on) {
+    g_prof_on = on != 0;
+    if (g_prof_on) {
+        for (auto& r : g_prof) {
+            (void)hipEventSynchronize(r.e2);
+            g_prof_pool.push_back(r.e0);
+            g_prof_pool.push_back(r.e1);
+            g_prof_pool.push_back(r.e2);
+        }
+        g_prof.clear();
+    }
+    return DM_OK;
+}
+
+int dm_profile_read(double* main_ms, double* fixup_ms, int64_t* launches, int reset) {
+    double a = 0.0, b = 0.0;
+    for (auto& r : g_prof) {
+        HIP_TRY(hipEventSynchronize(r.e2));
+        float t1 = 0.0f, t2 = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t1, r.e0, r.e1));
+        HIP_TRY(hipEventElapsedTime(&t2, r.e1, r.e2));
+        a += t1;
+        b += t2;
+    }
+    if (main_ms) *main_ms = a;
+    if (fixup_ms) *fixup_ms = b;
+    if (launches) *launches = (int64_t)g_prof.size();
+    if (reset) {
+        for (auto& r : g_prof) {
+            g_prof_pool.push_back(r.e0);
+            g_prof_pool.push_back(r.e1);
+            g_prof_pool.push_back(r.e2);
+        }
+        g_prof.clear();
     }
     return DM_OK;
 }

@@ -23,58 +23,6 @@ constexpr int kValuThreads = 512;
 constexpr int kLdsFloats = 16384;  // 64 KiB of points per staged chunk
 
 template <int DP>
-__device__ __forceinline__ void load_symbol(float (&y)[DP], const float* src, int D, bool active) {
-#pragma unroll
-    for (int d = 0; d < DP; ++d) y[d] = (active && d < D) ? src[d] : 0.0f;
-}
-
-// Exact log-sum-exp (log2 units, t_j = K - c d_j^2) of the subsets of label bit p,
-// with each subset shifted by its own maximum.  Returns L = log2 S^1 - log2 S^0.
-template <int DP>
-__device__ float exact_bit_llr2(const float (&y)[DP], const float* table, int M, int p, float c, float K) {
-    float mx0 = -INFINITY, mx1 = -INFINITY;
-    for (int j = 0; j < M; ++j) {
-        const float t = fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K);
-        if ((j >> p) & 1) mx1 = fmaxf(mx1, t);
-        else mx0 = fmaxf(mx0, t);
-    }
-    float s0 = 0.0f, s1 = 0.0f;
-    for (int j = 0; j < M; ++j) {
-        const float t = fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K);
-        if ((j >> p) & 1) s1 += hw_exp2(t - mx1);
-        else s0 += hw_exp2(t - mx0);
-    }
-    return (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
-}
-
-// MI term m - log2 sum_j 2^(t_j - t_tx), exact max shift.
-template <int DP>
-__device__ float exact_mi_term(const float (&y)[DP], const float* table, int M, int m, int txl, float c, float K) {
-    float mx = -INFINITY;
-    for (int j = 0; j < M; ++j) mx = fmaxf(mx, fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K));
-    float s = 0.0f;
-    for (int j = 0; j < M; ++j) s += hw_exp2(fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K) - mx);
-    const float ttx = fmaf(-c, sqdist<DP>(y, table + (size_t)txl * DP), K);
-    return (float)m - ((mx - ttx) + hw_log2(s));
-}
-
-// Recompute the flagged bits of one symbol; returns the GMI-term and MI-term corrections.
-template <int DP>
-__device__ void fixup_one(const LaunchArgs& a, const FixEntry& e, double& gcorr, double& mcorr) {
-    const SnrArg sa = a.snr[e.snr];
-    float y[DP];
-    load_symbol<DP>(y, sa.y + (size_t)e.n * a.D, a.D, true);
-    const int txl = a.tx ? tx_label(a, e.n) : 0;
-    for (int p = 0; p < a.m; ++p) {
-        if (!((e.mask >> p) & 1u)) continue;
-        const float L = exact_bit_llr2<DP>(y, a.table, a.M, p, sa.c, a.K);
-        if (sa.llr) sa.llr[(size_t)e.n * a.m + (a.m - 1 - p)] = L * 0.69314718055994531f;
-        if (a.tx) gcorr += (double)gmi_bit_term(L, (txl >> p) & 1);
-    }
-    if ((e.mask & kMiFlag) && a.tx) mcorr += (double)exact_mi_term<DP>(y, a.table, a.M, a.m, txl, sa.c, a.K);
-}
-
-template <int DP>
 __global__ __launch_bounds__(kValuThreads) void demap_valu_kernel(const LaunchArgs a) {
     extern __shared__ float lds[];
     const int M = a.M, m = a.m, D = a.D;
@@ -257,15 +205,18 @@ __global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a) {
 }
 
 template <int DP>
-hipError_t launch_valu_t(const LaunchArgs& a, int grid, int fix_grid, hipStream_t st) {
+hipError_t launch_valu_t(const LaunchArgs& a, int grid, hipStream_t st) {
     const int Mpad = a.M < 16 ? 16 : a.M;
     int chunk = (kLdsFloats / DP) & ~63;
     if (chunk >= Mpad) chunk = Mpad;
     const size_t lds = (size_t)chunk * DP * sizeof(float);
     hipLaunchKernelGGL(demap_valu_kernel<DP>, dim3(grid), dim3(kValuThreads), lds, st, a);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(fixup_kernel<DP>, dim3(fix_grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int DP>
+hipError_t launch_fixup_t(const LaunchArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(fixup_kernel<DP>, dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -278,20 +229,27 @@ int padded_dim(int D) {
 
 int valu_tile_symbols() { return kValuThreads; }
 
-hipError_t launch_demap_valu(const LaunchArgs& a, int grid, int fix_grid, hipStream_t st) {
-    switch (padded_dim(a.D)) {
-        case 1: return launch_valu_t<1>(a, grid, fix_grid, st);
-        case 2: return launch_valu_t<2>(a, grid, fix_grid, st);
-        case 3: return launch_valu_t<3>(a, grid, fix_grid, st);
-        case 4: return launch_valu_t<4>(a, grid, fix_grid, st);
-        case 5: return launch_valu_t<5>(a, grid, fix_grid, st);
-        case 6: return launch_valu_t<6>(a, grid, fix_grid, st);
-        case 7: return launch_valu_t<7>(a, grid, fix_grid, st);
-        case 8: return launch_valu_t<8>(a, grid, fix_grid, st);
-        case 16: return launch_valu_t<16>(a, grid, fix_grid, st);
-        case 32: return launch_valu_t<32>(a, grid, fix_grid, st);
-        default: return hipErrorInvalidValue;
+#define DM_DISPATCH_DP(FN, ...)                          \
+    switch (padded_dim(a.D)) {                          \
+        case 1: return FN<1>(__VA_ARGS__);              \
+        case 2: return FN<2>(__VA_ARGS__);              \
+        case 3: return FN<3>(__VA_ARGS__);              \
+        case 4: return FN<4>(__VA_ARGS__);              \
+        case 5: return FN<5>(__VA_ARGS__);              \
+        case 6: return FN<6>(__VA_ARGS__);              \
+        case 7: return FN<7>(__VA_ARGS__);              \
+        case 8: return FN<8>(__VA_ARGS__);              \
+        case 16: return FN<16>(__VA_ARGS__);            \
+        case 32: return FN<32>(__VA_ARGS__);            \
+        default: return hipErrorInvalidValue;           \
     }
+
+hipError_t launch_demap_valu(const LaunchArgs& a, int grid, hipStream_t st) {
+    DM_DISPATCH_DP(launch_valu_t, a, grid, st)
+}
+
+hipError_t launch_fixup(const LaunchArgs& a, int grid, hipStream_t st) {
+    DM_DISPATCH_DP(launch_fixup_t, a, grid, st)
 }
 
 }  // namespace dm

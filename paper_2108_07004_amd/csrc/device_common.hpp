@@ -104,4 +104,58 @@ __device__ __forceinline__ float sqdist(const float (&y)[D], const float* x) {
     return acc;
 }
 
+// ---- exact recomputation shared by every demapping kernel (far-subset fix-up) ----
+
+template <int DP>
+__device__ __forceinline__ void load_symbol(float (&y)[DP], const float* src, int D, bool active) {
+#pragma unroll
+    for (int d = 0; d < DP; ++d) y[d] = (active && d < D) ? src[d] : 0.0f;
+}
+
+// Exact log-sum-exp (log2 units, t_j = K - c d_j^2) of the subsets of label bit p,
+// with each subset shifted by its own maximum.  Returns L = log2 S^1 - log2 S^0.
+template <int DP>
+__device__ float exact_bit_llr2(const float (&y)[DP], const float* table, int M, int p, float c, float K) {
+    float mx0 = -INFINITY, mx1 = -INFINITY;
+    for (int j = 0; j < M; ++j) {
+        const float t = fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K);
+        if ((j >> p) & 1) mx1 = fmaxf(mx1, t);
+        else mx0 = fmaxf(mx0, t);
+    }
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int j = 0; j < M; ++j) {
+        const float t = fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K);
+        if ((j >> p) & 1) s1 += hw_exp2(t - mx1);
+        else s0 += hw_exp2(t - mx0);
+    }
+    return (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
+}
+
+// MI term m - log2 sum_j 2^(t_j - t_tx), exact max shift.
+template <int DP>
+__device__ float exact_mi_term(const float (&y)[DP], const float* table, int M, int m, int txl, float c, float K) {
+    float mx = -INFINITY;
+    for (int j = 0; j < M; ++j) mx = fmaxf(mx, fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K));
+    float s = 0.0f;
+    for (int j = 0; j < M; ++j) s += hw_exp2(fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K) - mx);
+    const float ttx = fmaf(-c, sqdist<DP>(y, table + (size_t)txl * DP), K);
+    return (float)m - ((mx - ttx) + hw_log2(s));
+}
+
+// Recompute the flagged bits of one symbol; returns the GMI-term and MI-term corrections.
+template <int DP>
+__device__ void fixup_one(const LaunchArgs& a, const FixEntry& e, double& gcorr, double& mcorr) {
+    const SnrArg sa = a.snr[e.snr];
+    float y[DP];
+    load_symbol<DP>(y, sa.y + (size_t)e.n * a.D, a.D, true);
+    const int txl = a.tx ? tx_label(a, e.n) : 0;
+    for (int p = 0; p < a.m; ++p) {
+        if (!((e.mask >> p) & 1u)) continue;
+        const float L = exact_bit_llr2<DP>(y, a.table, a.M, p, sa.c, a.K);
+        if (sa.llr) sa.llr[(size_t)e.n * a.m + (a.m - 1 - p)] = L * 0.69314718055994531f;
+        if (a.tx) gcorr += (double)gmi_bit_term(L, (txl >> p) & 1);
+    }
+    if ((e.mask & kMiFlag) && a.tx) mcorr += (double)exact_mi_term<DP>(y, a.table, a.M, a.m, txl, sa.c, a.K);
+}
+
 }  // namespace dm

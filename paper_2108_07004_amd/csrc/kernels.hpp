@@ -12,7 +12,10 @@ int padded_dim(int D);
 // Symbols per tile of the FP32 kernel (one lane per symbol).
 int valu_tile_symbols();
 
-// FP32 direct-difference demapper followed by the far-subset fix-up kernel.
-hipError_t launch_demap_valu(const LaunchArgs& a, int grid, int fix_grid, hipStream_t st);
+// FP32 direct-difference demapper (one lane per symbol, persistent grid).
+hipError_t launch_demap_valu(const LaunchArgs& a, int grid, hipStream_t st);
+
+// Exact recomputation of the queued (symbol, bit) pairs whose far-subset sum underflowed.
+hipError_t launch_fixup(const LaunchArgs& a, int grid, hipStream_t st);
 
 }  // namespace dm
