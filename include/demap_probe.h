@@ -36,6 +36,15 @@ int dm_probe_valu_rates(double* rates, void* stream);
 int dm_profile_enable(int on);
 int dm_profile_read(double* main_ms, double* fixup_ms, int64_t* launches, int reset);
 
+/*
+ * One MFMA product with the lane mapping the demapping kernels assume, for checking it.
+ *   dtype 0 = BF16, 1 = FP16 operands; shape 0 = v_mfma_f32_32x32x16 (A 32x16, B 16x32,
+ *   D 32x32), shape 1 = v_mfma_f32_16x16x32 (A 16x32, B 32x16, D 16x16).
+ *   A, B, D are HOST row-major FP32 arrays (A, B rounded to dtype).  Synchronous.
+ * Returns 0, -1 (bad argument), -3 (HIP error), -4 (allocation failed).
+ */
+int dm_probe_mfma_layout(int dtype, int shape, const float* A, const float* B, float* D);
+
 #ifdef __cplusplus
 }
 #endif

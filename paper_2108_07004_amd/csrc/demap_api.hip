@@ -31,6 +31,9 @@ struct dm_constellation {
     FixEntry* d_queue = nullptr;
     uint32_t queue_cap = 0;
     void* h_stage = nullptr;              // pinned: acc + fix_pairs
+    void* d_frag[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // MFMA point tables per precision
+    void* d_pv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};    // same operands per label [M][K]
+    float max_norm = 0.0f;                // max ||x||^2 (FP16 operand range check)
     std::mutex mu;
 };
 
@@ -148,6 +151,91 @@ LaunchArgs base_args(const dm_constellation* c, int64_t N) {
     return a;
 }
 
+uint16_t bf16_bits(float f) {  // round to nearest even
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+uint16_t f16_bits(float f) {
+    _Float16 h = (_Float16)f;
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+float f16_value(uint16_t b) {
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return (float)h;
+}
+
+// Point-side operand table of an MFMA precision in fragment order [tile][mfma][lane][8].
+// Row i of a 32-point tile carries label 32t + 16*((i>>2)&1) + 4*(i>>3) + (i&3).
+int ensure_frag(dm_constellation* c, int prec) {
+    if (c->d_frag[prec]) return DM_OK;
+    const bool bf = (prec == DM_PREC_BF16 || prec == DM_PREC_BF16X3);
+    const bool split = (prec == DM_PREC_BF16X3 || prec == DM_PREC_FP16X3);
+    const int D = c->D, M = c->M;
+    const int K = dm::mfma_slots(D, split), S = K / 16;
+    auto hi = [&](float v) { return bf ? bf16_bits(v) : f16_bits(v); };
+    auto val = [&](uint16_t b) { return bf ? bf16_value(b) : f16_value(b); };
+    auto lo = [&](float v) { return hi(v - val(hi(v))); };
+    std::vector<uint16_t> pv((size_t)M * K, 0);  // per label, K slots
+    for (int l = 0; l < M; ++l) {
+        const float* x = &c->h_table[(size_t)l * D];
+        double n = 0.0;
+        for (int d = 0; d < D; ++d) n += (double)x[d] * (double)x[d];
+        const float nn = -(float)n;
+        uint16_t* o = &pv[(size_t)l * K];
+        if (!split) {
+            for (int d = 0; d < D; ++d) o[d] = hi(x[d]);
+            o[D] = hi(nn);
+            o[D + 1] = hi(1.0f);
+        } else {
+            for (int d = 0; d < D; ++d) {
+                o[d] = hi(x[d]);
+                o[D + d] = hi(x[d]);
+                o[2 * D + d] = lo(x[d]);
+            }
+            o[3 * D] = hi(nn);
+            o[3 * D + 1] = hi(nn);
+            o[3 * D + 2] = lo(nn);
+            o[3 * D + 3] = hi(1.0f);
+            o[3 * D + 4] = hi(1.0f);
+        }
+    }
+    const int ntiles = M / 32;
+    std::vector<uint16_t> fr((size_t)ntiles * S * 64 * 8);
+    for (int t = 0; t < ntiles; ++t)
+        for (int sidx = 0; sidx < S; ++sidx)
+            for (int ln = 0; ln < 64; ++ln) {
+                const int i = ln % 32;
+                const int label = 32 * t + 16 * ((i >> 2) & 1) + 4 * (i >> 3) + (i & 3);
+                const int base = 16 * sidx + 8 * (ln / 32);
+                for (int v = 0; v < 8; ++v)
+                    fr[(((size_t)t * S + sidx) * 64 + ln) * 8 + v] = pv[(size_t)label * K + base + v];
+            }
+    void *d = nullptr, *dp = nullptr;
+    HIP_TRY(hipMalloc(&d, fr.size() * sizeof(uint16_t)));
+    hipError_t e = hipMalloc(&dp, pv.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(d, fr.data(), fr.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dp, pv.data(), pv.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        (void)hipFree(dp);
+        return hip_fail(e, "fragment table upload");
+    }
+    c->d_frag[prec] = d;
+    c->d_pv[prec] = dp;
+    return DM_OK;
+}
+
 float exponent_scale(double sigma2) { return (float)(1.4426950408889634 / (2.0 * sigma2)); }
 
 int validate_sigma2(double s2) {
@@ -160,8 +248,19 @@ int validate_sigma2(double s2) {
 // Run the demapper over up to kMaxSnrPerLaunch SNR points of one block.
 int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
               int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st) {
-    if (prec != DM_PREC_FP32) return fail(DM_EUNSUPPORTED, "precision %d is not available yet", prec);
-    const int tile = dm::valu_tile_symbols();
+    if (prec != DM_PREC_FP32) {
+        if (c->D > 8) return fail(DM_EUNSUPPORTED, "MFMA precisions support D <= 8 (D=%d)", c->D);
+        if (c->M < 32) return fail(DM_EUNSUPPORTED, "MFMA precisions need M >= 32 (M=%d)", c->M);
+        if (prec == DM_PREC_FP16 || prec == DM_PREC_FP16X3) {
+            if (c->max_norm >= 60000.0f) return fail(DM_EUNSUPPORTED, "point norms exceed the FP16 operand range");
+            for (int s = 0; s < n_snr; ++s)
+                if (exponent_scale(sigma2[s]) >= 30000.0f)
+                    return fail(DM_EUNSUPPORTED, "sigma2 %g is too small for FP16 operands", sigma2[s]);
+        }
+        int rr = ensure_frag(c, prec);
+        if (rr) return rr;
+    }
+    const int tile = prec == DM_PREC_FP32 ? dm::valu_tile_symbols() : dm::mfma_block_symbols();
     const int64_t tiles_per_snr = (N + tile - 1) / tile;
     int r = ensure_scratch(c, (uint64_t)N * n_snr);
     if (r) return r;
@@ -183,14 +282,15 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
         HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
     }
     HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
-    const int grid = persistent_grid(c, tiles_per_snr * n_snr, 2);
+    const int grid = persistent_grid(c, tiles_per_snr * n_snr, prec == DM_PREC_FP32 ? 2 : 1);
     const int fix_grid = c->cus * 4;
     ProfRec pr{nullptr, nullptr, nullptr};
     if (g_prof_on) {
         pr = ProfRec{prof_event(), prof_event(), prof_event()};
         if (pr.e0) HIP_TRY(hipEventRecord(pr.e0, st));
     }
-    HIP_TRY(dm::launch_demap_valu(a, grid, st));
+    if (prec == DM_PREC_FP32) HIP_TRY(dm::launch_demap_valu(a, grid, st));
+    else HIP_TRY(dm::launch_demap_mfma(a, prec, c->d_frag[prec], c->d_pv[prec], grid, st));
     if (pr.e1) HIP_TRY(hipEventRecord(pr.e1, st));
     HIP_TRY(dm::launch_fixup(a, fix_grid, st));
     if (pr.e2) {
@@ -242,6 +342,11 @@ int dm_constellation_create(const float* points, const uint16_t* labels, int32_t
         return hip_fail(e, "device query");
     }
     c->h_table.assign((size_t)M * D, 0.0f);
+    for (int j = 0; j < M; ++j) {
+        double n = 0.0;
+        for (int d = 0; d < D; ++d) n += (double)points[(size_t)j * D + d] * points[(size_t)j * D + d];
+        c->max_norm = std::max(c->max_norm, (float)n);
+    }
     std::vector<float> padded((size_t)M * c->DP, 0.0f);
     std::vector<uint16_t> r2l(labels, labels + M);
     for (int l = 0; l < M; ++l)
@@ -269,6 +374,8 @@ void dm_constellation_destroy(dm_constellation* c) {
     (void)hipFree(c->d_queue_count);
     (void)hipFree(c->d_queue);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
+    for (void* f : c->d_frag) (void)hipFree(f);
+    for (void* f : c->d_pv) (void)hipFree(f);
     delete c;
 }
 

@@ -18,4 +18,15 @@ hipError_t launch_demap_valu(const LaunchArgs& a, int grid, hipStream_t st);
 // Exact recomputation of the queued (symbol, bit) pairs whose far-subset sum underflowed.
 hipError_t launch_fixup(const LaunchArgs& a, int grid, hipStream_t st);
 
+// K slots (multiple of 16) of the MFMA operand vectors for dimensionality D.
+int mfma_slots(int D, bool split);
+
+// Symbols per block iteration of the MFMA kernel.
+int mfma_block_symbols();
+
+// MFMA demapper: prec 1 = BF16, 2 = FP16, 3 = BF16 split, 4 = FP16 split.  `frag` is the
+// point-side operand table in fragment order ([tile][mfma][lane] x 16 bytes); `pv` the same
+// operands per label ([label][K slots], 16-bit), read for the transmitted points.
+hipError_t launch_demap_mfma(const LaunchArgs& a, int prec, const void* frag, const void* pv, int grid, hipStream_t st);
+
 }  // namespace dm

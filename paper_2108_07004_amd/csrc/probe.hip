@@ -105,3 +105,60 @@ extern "C" int dm_probe_valu_rates(double* rates, void* stream) {
     rates[3] = (double)cus;
     return 0;
 }
+
+// ---- MFMA lane-layout check (gfx950): one 32x32x16 or 16x16x32 product with the fragment
+// mapping the demapping kernels assume, so a test can compare it with A @ B on the host.
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+template <typename T, typename V>
+__global__ __launch_bounds__(64) void probe_mfma_layout(const float* A, const float* B, float* Dm, int shape) {
+    const int l = threadIdx.x;
+    V a, b;
+    if (shape == 0) {  // 32x32x16: A 32x16 row-major, B 16x32 row-major, D 32x32
+        for (int v = 0; v < 8; ++v) {
+            a[v] = (T)A[(l % 32) * 16 + 8 * (l / 32) + v];
+            b[v] = (T)B[(8 * (l / 32) + v) * 32 + (l % 32)];
+        }
+        f32x16_t d = {};
+        if constexpr (sizeof(T) == 2 && __is_same(T, __bf16)) d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, d, 0, 0, 0);
+        else d = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, d, 0, 0, 0);
+        for (int r = 0; r < 16; ++r) Dm[(8 * (r / 4) + 4 * (l / 32) + (r % 4)) * 32 + (l % 32)] = d[r];
+    } else {  // 16x16x32: A 16x32, B 32x16, D 16x16
+        for (int v = 0; v < 8; ++v) {
+            a[v] = (T)A[(l % 16) * 32 + 8 * (l / 16) + v];
+            b[v] = (T)B[(8 * (l / 16) + v) * 16 + (l % 16)];
+        }
+        f32x4_t d = {};
+        if constexpr (__is_same(T, __bf16)) d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, d, 0, 0, 0);
+        else d = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, d, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) Dm[(4 * (l / 16) + r) * 16 + (l % 16)] = d[r];
+    }
+}
+
+}  // namespace
+
+extern "C" int dm_probe_mfma_layout(int dtype, int shape, const float* A, const float* B, float* Dout) {
+    if (!A || !B || !Dout || (dtype != 0 && dtype != 1) || (shape != 0 && shape != 1)) return -1;
+    const size_t na = 512, nb = 512, nd = shape == 0 ? 1024 : 256;
+    float *dA = nullptr, *dB = nullptr, *dD = nullptr;
+    if (hipMalloc(&dA, na * 4) != hipSuccess || hipMalloc(&dB, nb * 4) != hipSuccess ||
+        hipMalloc(&dD, nd * 4) != hipSuccess) {
+        hipFree(dA);
+        hipFree(dB);
+        return -4;
+    }
+    hipMemcpy(dA, A, na * 4, hipMemcpyHostToDevice);
+    hipMemcpy(dB, B, nb * 4, hipMemcpyHostToDevice);
+    if (dtype == 0) hipLaunchKernelGGL((probe_mfma_layout<__bf16, bf16x8_t>), dim3(1), dim3(64), 0, 0, dA, dB, dD, shape);
+    else hipLaunchKernelGGL((probe_mfma_layout<_Float16, f16x8_t>), dim3(1), dim3(64), 0, 0, dA, dB, dD, shape);
+    hipError_t e = hipMemcpy(Dout, dD, nd * 4, hipMemcpyDeviceToHost);
+    hipFree(dA);
+    hipFree(dB);
+    hipFree(dD);
+    return e == hipSuccess ? 0 : -3;
+}

@@ -232,3 +232,17 @@ def awgn_torch(points, tx, z, sigma2):
     x = p64[tx.to(torch.int64)]
     s = math.sqrt(float(sigma2))
     return (x + (z * s)).to(torch.float32)
+
+
+def mlp_init_weights(D: int, H: int, m: int, config: int = 4) -> dict:
+    """Seeded initial weights of the learned demapper's MLP (FP32 master copies).
+
+    Uniform(-b, b) with b = 0.5 sqrt(6 / fan_in); zero biases.  Row-major W (fan_in, fan_out).
+    """
+    g = rng(config, "mlp_init", D, H, m)
+    w = {}
+    for name, fi, fo in (("1", D + 1, H), ("2", H, H), ("3", H, m)):
+        b = 0.5 * math.sqrt(6.0 / fi)
+        w["W" + name] = g.uniform(-b, b, (fi, fo)).astype(np.float32)
+        w["b" + name] = np.zeros(fo, dtype=np.float32)
+    return w
