@@ -145,9 +145,9 @@ LaunchArgs base_args(const dm_constellation* c, int64_t N) {
     a.K = (float)(123 - c->m);
     a.flag_thresh = std::ldexp(1.0f, c->m - 102);
     a.near_thresh = std::ldexp(1.0f, c->m - 42);
-    a.queue = c->d_queue;
-    a.queue_count = c->d_queue_count;
-    a.queue_cap = c->queue_cap;
+    a.sinks.queue = c->d_queue;
+    a.sinks.queue_count = c->d_queue_count;
+    a.sinks.queue_cap = c->queue_cap;
     return a;
 }
 
@@ -269,9 +269,9 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
     a.tiles_per_snr = tiles_per_snr;
     a.n_snr = n_snr;
     a.want_llr = llr ? 1 : 0;
-    a.acc = want_acc ? c->d_acc : nullptr;
-    a.fix_pairs = want_acc ? c->d_fix_pairs : nullptr;
-    a.bad_tx = want_acc ? c->d_fix_pairs + dm::kMaxSnrPerLaunch : nullptr;
+    a.sinks.acc = want_acc ? c->d_acc : nullptr;
+    a.sinks.fix_pairs = want_acc ? c->d_fix_pairs : nullptr;
+    a.sinks.bad_tx = want_acc ? c->d_fix_pairs + dm::kMaxSnrPerLaunch : nullptr;
     for (int s = 0; s < n_snr; ++s) {
         a.snr[s].y = y[s];
         a.snr[s].llr = llr ? llr[s] : nullptr;

@@ -6,53 +6,94 @@
 namespace dm {
 
 constexpr int kMaxSnrPerLaunch = 32;  // SNR points per launch (kernel-argument block stays < 1 KiB)
-constexpr int kAccSlots = 64;         // fixed-point accumulator slots per SNR point (spreads atomics)
+constexpr int kAccSlots = 64;         // fixed-point accumulator slots per block (spreads atomics)
 constexpr double kFixScale = 268435456.0;  // 2^28: GMI/MI sums are accumulated as int64 * 2^-28
 constexpr uint32_t kMiFlag = 0x80000000u;  // fix-up mask bit: recompute the MI term
 
 // One symbol whose far-subset sums underflowed the shared exponent window.
 struct FixEntry {
-    uint32_t n;     // symbol index within the block
-    uint32_t snr;   // SNR index within the launch
+    uint32_t n;     // symbol index within its block
+    uint32_t tag;   // block (SNR point or instance) the symbol belongs to
     uint32_t mask;  // bit p set: recompute label bit p; kMiFlag: recompute the MI term
     uint32_t pad;
+};
+
+// One received block: a constellation at one noise level with its data.
+struct BlockView {
+    const float* table;          // M x DP FP32 points in label order (row j has label j)
+    const uint16_t* row2label;   // M: label of each caller row
+    const uint16_t* tx;          // N transmitted caller rows, or null (no GMI/MI)
+    const float* y;              // N x D received symbols
+    float* llr;                  // N x m output or null
+    int64_t N;
+    int32_t M, D, m;
+    float c;                     // log2(e) / (2 sigma2), rounded once from FP64
+    float K;                     // exponent offset: e_j = 2^(K - c ||y - x_j||^2)
+    float flag_thresh;           // 2^(m-102): a subset sum below this is recomputed
+    float near_thresh;           // 2^(m-42): GMI-only shortcut bound for the near subset
+    int32_t want_llr;
+    int32_t tag;                 // accumulator row and fix-up tag of this block
+};
+
+// Where kernels put results shared across blocks.
+struct Sinks {
+    unsigned long long* acc;     // [tags][kAccSlots][2] int64 fixed-point GMI / MI sums, or null
+    uint32_t* fix_pairs;         // [tags] count of (symbol, bit) pairs sent to the fix-up, or null
+    uint32_t* bad_tx;            // set to 1 when a transmitted index is >= M (clamped, reported)
+    FixEntry* queue;
+    uint32_t* queue_count;
+    uint32_t queue_cap;
 };
 
 struct SnrArg {
     const float* y;  // N x D received block
     float* llr;      // N x m output or null
-    float c;         // log2(e) / (2 sigma2), rounded once from FP64
+    float c;         // log2(e) / (2 sigma2)
     int32_t pad;
 };
 
+// Multi-SNR launch over one constellation and one transmitted block.
 struct LaunchArgs {
-    const float* table;          // M x D FP32 points in label order (row j has label j)
-    const uint16_t* row2label;   // M: label of each caller row
-    const uint16_t* tx;          // N transmitted caller rows, or null (no GMI/MI)
+    const float* table;
+    const uint16_t* row2label;
+    const uint16_t* tx;
     int64_t N;
     int64_t tiles_per_snr;
     int32_t M, D, m, n_snr;
-    float K;                     // exponent offset: e_j = 2^(K - c ||y - x_j||^2)
-    float flag_thresh;           // 2^(m-102): a subset sum below this is recomputed
-    float near_thresh;           // 2^(m-42): GMI-only shortcut bound for the near subset
+    float K, flag_thresh, near_thresh;
     int32_t want_llr;
-    unsigned long long* acc;     // [n_snr][kAccSlots][2] int64 fixed-point GMI / MI sums
-    uint32_t* fix_pairs;         // [n_snr] count of (symbol, bit) pairs sent to the fix-up
-    uint32_t* bad_tx;            // set to 1 when a transmitted index is >= M (clamped, reported)
-    FixEntry* queue;
-    uint32_t* queue_count;
-    uint32_t queue_cap;
+    Sinks sinks;
     SnrArg snr[kMaxSnrPerLaunch];
 };
 
+__device__ __forceinline__ BlockView view_snr(const LaunchArgs& a, int s) {
+    BlockView v;
+    v.table = a.table;
+    v.row2label = a.row2label;
+    v.tx = a.tx;
+    v.y = a.snr[s].y;
+    v.llr = a.snr[s].llr;
+    v.N = a.N;
+    v.M = a.M;
+    v.D = a.D;
+    v.m = a.m;
+    v.c = a.snr[s].c;
+    v.K = a.K;
+    v.flag_thresh = a.flag_thresh;
+    v.near_thresh = a.near_thresh;
+    v.want_llr = a.want_llr;
+    v.tag = s;
+    return v;
+}
+
 // Label of the transmitted row; an out-of-range row is clamped and reported.
-__device__ __forceinline__ int tx_label(const LaunchArgs& a, int64_t n) {
-    uint32_t r = a.tx[n];
-    if (r >= (uint32_t)a.M) {
-        if (a.bad_tx) atomicOr(a.bad_tx, 1u);
+__device__ __forceinline__ int tx_label(const BlockView& b, const Sinks& k, int64_t n) {
+    uint32_t r = b.tx[n];
+    if (r >= (uint32_t)b.M) {
+        if (k.bad_tx) atomicOr(k.bad_tx, 1u);
         r = 0;
     }
-    return (int)a.row2label[r];
+    return (int)b.row2label[r];
 }
 
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -142,20 +183,97 @@ __device__ float exact_mi_term(const float (&y)[DP], const float* table, int M, 
     return (float)m - ((mx - ttx) + hw_log2(s));
 }
 
-// Recompute the flagged bits of one symbol; returns the GMI-term and MI-term corrections.
+// Recompute the flagged bits of one symbol in one lane; returns the GMI / MI corrections.
 template <int DP>
-__device__ void fixup_one(const LaunchArgs& a, const FixEntry& e, double& gcorr, double& mcorr) {
-    const SnrArg sa = a.snr[e.snr];
+__device__ void fixup_one(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask, double& gcorr,
+                          double& mcorr) {
     float y[DP];
-    load_symbol<DP>(y, sa.y + (size_t)e.n * a.D, a.D, true);
-    const int txl = a.tx ? tx_label(a, e.n) : 0;
-    for (int p = 0; p < a.m; ++p) {
-        if (!((e.mask >> p) & 1u)) continue;
-        const float L = exact_bit_llr2<DP>(y, a.table, a.M, p, sa.c, a.K);
-        if (sa.llr) sa.llr[(size_t)e.n * a.m + (a.m - 1 - p)] = L * 0.69314718055994531f;
-        if (a.tx) gcorr += (double)gmi_bit_term(L, (txl >> p) & 1);
+    load_symbol<DP>(y, b.y + (size_t)n * b.D, b.D, true);
+    const int txl = b.tx ? tx_label(b, k, n) : 0;
+    for (int p = 0; p < b.m; ++p) {
+        if (!((mask >> p) & 1u)) continue;
+        const float L = exact_bit_llr2<DP>(y, b.table, b.M, p, b.c, b.K);
+        if (b.llr) b.llr[(size_t)n * b.m + (b.m - 1 - p)] = L * 0.69314718055994531f;
+        if (b.tx) gcorr += (double)gmi_bit_term(L, (txl >> p) & 1);
     }
-    if ((e.mask & kMiFlag) && a.tx) mcorr += (double)exact_mi_term<DP>(y, a.table, a.M, a.m, txl, sa.c, a.K);
+    if ((mask & kMiFlag) && b.tx) mcorr += (double)exact_mi_term<DP>(y, b.table, b.M, b.m, txl, b.c, b.K);
+}
+
+// ---- wave-cooperative fix-up: one wavefront per queued symbol, lanes split the points ----
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Exact subset log-sum-exps of label bit p (p < 0: all points into subset 0) for one symbol,
+// computed by the whole wavefront; returns (log2 S^1 - log2 S^0) and, via lse0, log2 S^0.
+template <int DP>
+__device__ float wave_exact_llr2(const float (&y)[DP], const float* table, int M, int p, float c, float K,
+                                 float& lse0) {
+    const int lane = threadIdx.x & 63;
+    float mx0 = -INFINITY, mx1 = -INFINITY;
+    for (int j = lane; j < M; j += 64) {
+        const float t = fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K);
+        if (p >= 0 && ((j >> p) & 1)) mx1 = fmaxf(mx1, t);
+        else mx0 = fmaxf(mx0, t);
+    }
+    mx0 = wave_max_f(mx0);
+    mx1 = wave_max_f(mx1);
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int j = lane; j < M; j += 64) {
+        const float t = fmaf(-c, sqdist<DP>(y, table + (size_t)j * DP), K);
+        if (p >= 0 && ((j >> p) & 1)) s1 += hw_exp2(t - mx1);
+        else s0 += hw_exp2(t - mx0);
+    }
+    s0 = wave_sum_f(s0);
+    s1 = wave_sum_f(s1);
+    lse0 = mx0 + hw_log2(s0);
+    return (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
+}
+
+// Recompute the flagged bits (and the MI term if asked) of one queued symbol with a whole
+// wavefront; lane 0 receives the GMI-term and MI-term corrections.
+template <int DP>
+__device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask, double& gcorr,
+                           double& mcorr) {
+    const int lane = threadIdx.x & 63;
+    float y[DP];
+    load_symbol<DP>(y, b.y + (size_t)n * b.D, b.D, true);
+    const int txl = b.tx ? tx_label(b, k, n) : 0;
+    for (int p = 0; p < b.m; ++p) {
+        if (!((mask >> p) & 1u)) continue;
+        float lse0;
+        const float L = wave_exact_llr2<DP>(y, b.table, b.M, p, b.c, b.K, lse0);
+        if (lane == 0) {
+            if (b.llr) b.llr[(size_t)n * b.m + (b.m - 1 - p)] = L * 0.69314718055994531f;
+            if (b.tx) gcorr += (double)gmi_bit_term(L, (txl >> p) & 1);
+        }
+    }
+    if ((mask & kMiFlag) && b.tx) {
+        float lse_all;
+        (void)wave_exact_llr2<DP>(y, b.table, b.M, -1, b.c, b.K, lse_all);
+        const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
+        if (lane == 0) mcorr += (double)((float)b.m - (lse_all - ttx));
+    }
+}
+
+// Queue a symbol for the fix-up; when the queue is full the calling lane recomputes it in
+// place (slow but exact) and the corrections come back through gc / mc.
+template <int DP>
+__device__ __forceinline__ void queue_or_fix(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask,
+                                             double& gc, double& mc) {
+    if (k.fix_pairs) atomicAdd(k.fix_pairs + b.tag, (uint32_t)__popc(mask & 0xFFFFu));
+    const uint32_t slot = atomicAdd(k.queue_count, 1u);
+    if (slot < k.queue_cap) k.queue[slot] = FixEntry{n, (uint32_t)b.tag, mask, 0u};
+    else fixup_one<DP>(b, k, n, mask, gc, mc);
 }
 
 }  // namespace dm

@@ -1,0 +1,103 @@
+"""Pins of the FP64 MLP oracle (learned demapper network), CPU only.
+
+* gradients against central finite differences of the loss (relative error <= 1e-7);
+* GELU (tanh form) against the erf form within the approximation's known bound and its
+  derivative against finite differences;
+* the soft-BCE loss is zero at its target and positive elsewhere (Gibbs), with a zero
+  gradient there;
+* Adam's first step equals -lr * g / (|g| + eps) element-wise (closed form);
+* a few Adam steps on a fixed batch lower the loss.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import workloads as W
+from oracle import mlp
+
+
+def _tiny(seed=3, D=2, H=5, m=3, B=7):
+    g = np.random.default_rng(seed)
+    w = {"W1": g.normal(0, 0.7, (D + 1, H)), "b1": g.normal(0, 0.1, H), "W2": g.normal(0, 0.5, (H, H)),
+         "b2": g.normal(0, 0.1, H), "W3": g.normal(0, 0.5, (H, m)), "b3": g.normal(0, 0.1, m)}
+    X = g.normal(0, 1, (B, D + 1))
+    T = g.normal(0, 3, (B, m))
+    return w, X, T
+
+
+def test_gradients_match_finite_differences():
+    w, X, T = _tiny()
+    out, cache = mlp.forward(w, X)
+    g = mlp.backward(w, cache, out, T)
+    h = 1e-6
+    for k in w:
+        flat = w[k].reshape(-1)
+        num = np.empty_like(flat)
+        for i in range(flat.size):
+            old = flat[i]
+            flat[i] = old + h
+            lp = mlp.loss(mlp.forward(w, X)[0], T)
+            flat[i] = old - h
+            lm = mlp.loss(mlp.forward(w, X)[0], T)
+            flat[i] = old
+            num[i] = (lp - lm) / (2 * h)
+        ana = g[k].reshape(-1)
+        err = np.max(np.abs(num - ana)) / max(np.max(np.abs(ana)), 1e-12)
+        assert err <= 1e-7, (k, err)
+
+
+def test_gelu_tanh_form_and_derivative():
+    x = np.linspace(-6, 6, 2001)
+    exact = 0.5 * x * (1 + erf(x / math.sqrt(2)))
+    assert np.max(np.abs(mlp.gelu(x) - exact)) < 1e-3  # the tanh form's known accuracy
+    h = 1e-6
+    num = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.max(np.abs(num - mlp.gelu_grad(x))) < 1e-8
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+
+
+def test_soft_bce_minimum_at_target():
+    g = np.random.default_rng(5)
+    T = g.normal(0, 5, (50, 4))
+    assert abs(mlp.loss(T, T)) < 1e-12
+    for _ in range(5):
+        O = T + g.normal(0, 1, T.shape)
+        assert mlp.loss(O, T) > 0
+    d = mlp.sigmoid(T) - mlp.sigmoid(T)
+    assert np.all(d == 0)
+
+
+def test_adam_first_step_closed_form():
+    w, X, T = _tiny()
+    out, cache = mlp.forward(w, X)
+    g = mlp.backward(w, cache, out, T)
+    w0 = {k: v.copy() for k, v in w.items()}
+    mlp.adam_step(w, g, {}, lr=1e-3, step=1)
+    for k in w:
+        expect = w0[k] - 1e-3 * g[k] / (np.abs(g[k]) + 1e-8)
+        assert np.allclose(w[k], expect, rtol=0, atol=1e-15)
+
+
+def test_training_lowers_the_loss():
+    w, X, _ = _tiny(B=64)
+    teacher, _, _ = _tiny(seed=11)
+    T = 4.0 * mlp.forward(teacher, X)[0]  # learnable targets
+    state = {}
+    l0 = mlp.loss(mlp.forward(w, X)[0], T)
+    for step in range(1, 201):
+        out, cache = mlp.forward(w, X)
+        mlp.adam_step(w, mlp.backward(w, cache, out, T), state, lr=1e-2, step=step)
+    assert mlp.loss(mlp.forward(w, X)[0], T) < 0.5 * l0
+
+
+def test_seeded_initial_weights_shapes():
+    w = W.mlp_init_weights(8, 256, 11)
+    assert w["W1"].shape == (9, 256) and w["W2"].shape == (256, 256) and w["W3"].shape == (256, 11)
+    assert all(v.dtype == np.float32 for v in w.values())
+    assert np.all(w["b1"] == 0) and abs(float(np.max(np.abs(w["W2"]))) - 0.5 * math.sqrt(6 / 256)) < 1e-3
+    w2 = W.mlp_init_weights(8, 256, 11)
+    assert all(np.array_equal(w[k], w2[k]) for k in w)
