@@ -102,6 +102,54 @@ int dm_gmi_estimate(const dm_constellation* c, int n_snr, const double* sigma2,
                     const float* const* y, const uint16_t* tx, int64_t N, float* const* llr,
                     double* gmi, double* mi, int prec, void* stream);
 
+/*
+ * Batched demapping of many instances (constellation, noise level, block) of uneven M, D and
+ * N in one persistent launch (the GMI of many candidate constellations, as the paper's
+ * shaping search evaluates, Sec. 5).  All instances share one operand precision `prec`;
+ * each instance runs the FP32 direct-difference body or the MFMA body, chosen per
+ * (M, D, prec) by timing both when DM_PLAN_AUTOTUNE is set (results cached per GPU arch in
+ * the file named by the environment variable DM_AUTOTUNE_CACHE, if set), by a fixed rule
+ * otherwise, or forced with DM_PLAN_FORCE_VALU / DM_PLAN_FORCE_MFMA.
+ * Limits: D <= 8 and M <= 4096 per instance (M <= 2048 for split MFMA operands).
+ */
+typedef struct dm_instance {
+    const dm_constellation* c;  /* uploaded constellation (not owned) */
+    double sigma2;              /* noise variance per real dimension, > 0 */
+    const float* y;             /* DEVICE, N x D received symbols */
+    const uint16_t* tx;         /* DEVICE, N transmitted row indices, or NULL (no GMI / MI) */
+    int64_t N;
+    float* llr;                 /* DEVICE, N x m LLR output (nats), or NULL */
+} dm_instance;
+
+enum { DM_PLAN_AUTOTUNE = 1, DM_PLAN_FORCE_VALU = 2, DM_PLAN_FORCE_MFMA = 4 };
+
+typedef struct dm_plan dm_plan;
+
+/*
+ * Build a plan for n_inst instances (copied; their device buffers must stay valid for the
+ * plan's lifetime): autotune if asked, split the work list into one cost-balanced contiguous
+ * segment per compute unit, allocate all scratch and capture zero-fill + batched kernel +
+ * fix-up into a hipGraph.  Synchronous (runs timing launches when autotuning).
+ * Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_EHIP, DM_ENOMEM.
+ */
+int dm_plan_create(const dm_instance* inst, int n_inst, int prec, int flags, dm_plan** out);
+
+/* Replay the plan's graph on `stream` (asynchronous; allocates nothing). */
+int dm_plan_launch(dm_plan* plan, void* stream);
+
+/* Wait for `stream`, then return per-instance GMI and MI (HOST arrays of n_inst; NaN for
+ * instances without tx or with N == 0) and fix-up pair counts (HOST int64, or NULL). */
+int dm_plan_results(dm_plan* plan, double* gmi, double* mi, int64_t* fixup_pairs, void* stream);
+
+/* Per-instance kernel body chosen (0 = FP32, 1 = MFMA) and its cost in ns per (symbol, point). */
+int dm_plan_info(const dm_plan* plan, int* kinds, double* ns_per_pair);
+
+void dm_plan_destroy(dm_plan* plan);
+
+/* One-shot: create, launch, read results, destroy (synchronous). */
+int dm_demap_batched(const dm_instance* inst, int n_inst, int prec, int flags, double* gmi, double* mi,
+                     void* stream);
+
 /* Number of (symbol, bit) pairs that the last call on this thread sent through the
  * far-subset underflow fix-up, per SNR point (HOST array of n_snr, may be NULL).
  * Returns the total, or a negative DM_E* if no call has run on this thread. */

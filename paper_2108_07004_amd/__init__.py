@@ -16,8 +16,8 @@ from typing import Sequence
 
 import numpy as np
 
-__all__ = ["Constellation", "DemapError", "PREC", "demap_llr", "gmi_estimate", "last_fixup_count",
-           "library_path", "load_library", "probe_valu_rates", "profile_enable", "profile_read"]
+__all__ = ["Constellation", "DemapError", "PREC", "Plan", "demap_batched", "demap_llr", "gmi_estimate",
+           "last_fixup_count", "library_path", "load_library", "probe_valu_rates", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}
@@ -61,6 +61,18 @@ def load_library():
     lib.dm_profile_enable.restype = I
     lib.dm_profile_read.argtypes = [P, P, P, I]
     lib.dm_profile_read.restype = I
+    lib.dm_plan_create.argtypes = [P, I, I, I, ctypes.POINTER(P)]
+    lib.dm_plan_create.restype = I
+    lib.dm_plan_launch.argtypes = [P, P]
+    lib.dm_plan_launch.restype = I
+    lib.dm_plan_results.argtypes = [P, P, P, P, P]
+    lib.dm_plan_results.restype = I
+    lib.dm_plan_info.argtypes = [P, P, P]
+    lib.dm_plan_info.restype = I
+    lib.dm_plan_destroy.argtypes = [P]
+    lib.dm_plan_destroy.restype = None
+    lib.dm_demap_batched.argtypes = [P, I, I, I, P, P, P]
+    lib.dm_demap_batched.restype = I
     lib.dm_last_error.restype = ctypes.c_char_p
     lib.dm_version.restype = ctypes.c_char_p
     _lib = lib
@@ -195,3 +207,88 @@ def profile_read(reset: bool = False):
     n = ctypes.c_int64()
     _check(load_library().dm_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n), 1 if reset else 0))
     return a.value, b.value, n.value
+
+
+PLAN_AUTOTUNE, PLAN_FORCE_VALU, PLAN_FORCE_MFMA = 1, 2, 4
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_void_p), ("sigma2", ctypes.c_double), ("y", ctypes.c_void_p),
+                ("tx", ctypes.c_void_p), ("N", ctypes.c_int64), ("llr", ctypes.c_void_p)]
+
+
+def _instances(items):
+    """items: sequence of (Constellation, sigma2, y, tx or None, llr or None) -> ctypes array."""
+    arr = (_Instance * len(items))()
+    for i, (c, s2, y, tx, llr) in enumerate(items):
+        N = int(y.shape[0])
+        arr[i].c = c.handle
+        arr[i].sigma2 = float(s2)
+        arr[i].y = _dev_tensor(y, ("float32",), (N, c.D), "y").value
+        arr[i].tx = None if tx is None else _dev_tensor(tx, ("int16", "uint16"), (N,), "tx").value
+        arr[i].N = N
+        arr[i].llr = None if llr is None else _dev_tensor(llr, ("float32",), (N, c.m), "llr").value
+    return arr
+
+
+class Plan:
+    """Batched plan over instances (Constellation, sigma2, y, tx, llr) — dm_plan_create.
+
+    The plan keeps references to every tensor it was built with (their memory must stay valid).
+    """
+
+    def __init__(self, items, prec: str = "fp16x3", autotune: bool = True, force: str | None = None):
+        self._items = list(items)
+        flags = PLAN_AUTOTUNE if autotune else 0
+        if force == "valu":
+            flags = PLAN_FORCE_VALU
+        elif force == "mfma":
+            flags = PLAN_FORCE_MFMA
+        self._arr = _instances(self._items)
+        h = ctypes.c_void_p()
+        _check(load_library().dm_plan_create(ctypes.cast(self._arr, ctypes.c_void_p), len(self._items), PREC[prec],
+                                             flags, ctypes.byref(h)))
+        self._h = h
+        self.n = len(self._items)
+
+    def launch(self, stream=None):
+        _check(load_library().dm_plan_launch(self._h, _stream_handle(stream)))
+
+    def results(self, stream=None):
+        g = np.empty(self.n, dtype=np.float64)
+        mi = np.empty(self.n, dtype=np.float64)
+        fx = np.empty(self.n, dtype=np.int64)
+        _check(load_library().dm_plan_results(self._h, g.ctypes.data_as(ctypes.c_void_p),
+                                              mi.ctypes.data_as(ctypes.c_void_p), fx.ctypes.data_as(ctypes.c_void_p),
+                                              _stream_handle(stream)))
+        return g, mi, fx
+
+    def info(self):
+        kinds = np.empty(self.n, dtype=np.int32)
+        ns = np.empty(self.n, dtype=np.float64)
+        _check(load_library().dm_plan_info(self._h, kinds.ctypes.data_as(ctypes.c_void_p),
+                                           ns.ctypes.data_as(ctypes.c_void_p)))
+        return kinds, ns
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().dm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def demap_batched(items, prec: str = "fp16x3", autotune: bool = False, stream=None):
+    """One-shot batched GMI/MI (dm_demap_batched); returns (gmi, mi) NumPy arrays."""
+    arr = _instances(list(items))
+    n = len(arr)
+    g = np.empty(n, dtype=np.float64)
+    mi = np.empty(n, dtype=np.float64)
+    _check(load_library().dm_demap_batched(ctypes.cast(arr, ctypes.c_void_p), n, PREC[prec],
+                                           PLAN_AUTOTUNE if autotune else 0, g.ctypes.data_as(ctypes.c_void_p),
+                                           mi.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)))
+    return g, mi

@@ -1,0 +1,56 @@
+// Library-internal host declarations shared by the C-ABI sources (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/demap.h"
+#include "device_common.hpp"
+
+struct dm_constellation {
+    int M = 0, D = 0, m = 0, DP = 0, device = 0, cus = 0;
+    float* d_table = nullptr;          // M x DP FP32, label order, zero-padded columns
+    uint16_t* d_row2label = nullptr;   // M
+    std::vector<float> h_table;        // host copy of the label-order table (M x D)
+    // scratch (grow-only), shared by calls on this constellation
+    unsigned long long* d_acc = nullptr;  // kMaxSnrPerLaunch x kAccSlots x 2
+    uint32_t* d_fix_pairs = nullptr;      // kMaxSnrPerLaunch + 1 (last word: bad-tx flag)
+    uint32_t* d_queue_count = nullptr;
+    dm::FixEntry* d_queue = nullptr;
+    uint32_t queue_cap = 0;
+    void* h_stage = nullptr;              // pinned: acc + fix_pairs
+    void* d_frag[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // MFMA point tables per precision
+    void* d_pv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};    // same operands per label [M][K]
+    // Batched-launch copies with the row stride padded to 8 (D <= 8).
+    float* d_table8 = nullptr;
+    void* d_frag8[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    void* d_pv8[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float max_norm = 0.0f;                // max ||x||^2 (FP16 operand range check)
+    std::mutex mu;
+};
+
+namespace dmapi {
+
+// Record a message for dm_last_error() and return `code`.
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+int check_device_ptr(const void* p, const char* name, int device);
+int check_current_device(const dm_constellation* c);
+int validate_sigma2(double s2);
+float exponent_scale(double sigma2);
+
+// MFMA point-operand tables of a precision (pad8: row layout padded to D = 8).
+int ensure_frag(dm_constellation* c, int prec, bool pad8);
+int ensure_table8(dm_constellation* c);
+
+}  // namespace dmapi
+
+#define DM_HIP_TRY(expr)                                          \
+    do {                                                          \
+        hipError_t _e = (expr);                                   \
+        if (_e != hipSuccess) return dmapi::hip_fail(_e, #expr);  \
+    } while (0)

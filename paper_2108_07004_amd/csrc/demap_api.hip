@@ -13,31 +13,14 @@
 
 #include "../../include/demap.h"
 #include "../../include/demap_probe.h"
+#include "api_internal.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
 using dm::FixEntry;
 using dm::LaunchArgs;
 
-struct dm_constellation {
-    int M = 0, D = 0, m = 0, DP = 0, device = 0, cus = 0;
-    float* d_table = nullptr;          // M x DP FP32, label order, zero-padded columns
-    uint16_t* d_row2label = nullptr;   // M
-    std::vector<float> h_table;        // host copy of the label-order table (M x D)
-    // scratch (grow-only), shared by calls on this constellation
-    unsigned long long* d_acc = nullptr;  // kMaxSnrPerLaunch x kAccSlots x 2
-    uint32_t* d_fix_pairs = nullptr;      // kMaxSnrPerLaunch + 1 (last word: bad-tx flag)
-    uint32_t* d_queue_count = nullptr;
-    FixEntry* d_queue = nullptr;
-    uint32_t queue_cap = 0;
-    void* h_stage = nullptr;              // pinned: acc + fix_pairs
-    void* d_frag[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // MFMA point tables per precision
-    void* d_pv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};    // same operands per label [M][K]
-    float max_norm = 0.0f;                // max ||x||^2 (FP16 operand range check)
-    std::mutex mu;
-};
-
-namespace {
+namespace dmapi {
 
 thread_local std::string g_err;
 thread_local std::vector<int64_t> g_fix_counts;
@@ -76,11 +59,6 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(DM_EHIP, "%s failed: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr)                                  \
-    do {                                               \
-        hipError_t _e = (expr);                        \
-        if (_e != hipSuccess) return hip_fail(_e, #expr); \
-    } while (0)
 
 constexpr size_t kStageBytes =
     sizeof(unsigned long long) * dm::kMaxSnrPerLaunch * dm::kAccSlots * 2 + sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1);
@@ -102,21 +80,21 @@ int check_device_ptr(const void* p, const char* name, int device) {
 
 int check_current_device(const dm_constellation* c) {
     int dev = -1;
-    HIP_TRY(hipGetDevice(&dev));
+    DM_HIP_TRY(hipGetDevice(&dev));
     if (dev != c->device) return fail(DM_EINVAL, "current device %d differs from the constellation's device %d", dev, c->device);
     return DM_OK;
 }
 
 int ensure_scratch(dm_constellation* c, uint64_t want_queue) {
     if (!c->d_acc) {
-        HIP_TRY(hipMalloc(&c->d_acc, sizeof(unsigned long long) * dm::kMaxSnrPerLaunch * dm::kAccSlots * 2));
-        HIP_TRY(hipMalloc(&c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1)));
-        HIP_TRY(hipMalloc(&c->d_queue_count, sizeof(uint32_t)));
-        HIP_TRY(hipHostMalloc(&c->h_stage, kStageBytes, hipHostMallocDefault));
+        DM_HIP_TRY(hipMalloc(&c->d_acc, sizeof(unsigned long long) * dm::kMaxSnrPerLaunch * dm::kAccSlots * 2));
+        DM_HIP_TRY(hipMalloc(&c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1)));
+        DM_HIP_TRY(hipMalloc(&c->d_queue_count, sizeof(uint32_t)));
+        DM_HIP_TRY(hipHostMalloc(&c->h_stage, kStageBytes, hipHostMallocDefault));
     }
     const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(want_queue, 1024), 1u << 22);
     if (cap > c->queue_cap) {
-        if (c->d_queue) HIP_TRY(hipFree(c->d_queue));
+        if (c->d_queue) DM_HIP_TRY(hipFree(c->d_queue));
         c->d_queue = nullptr;
         c->queue_cap = 0;
         if (hipMalloc(&c->d_queue, sizeof(FixEntry) * cap) != hipSuccess) {
@@ -177,18 +155,21 @@ float f16_value(uint16_t b) {
 
 // Point-side operand table of an MFMA precision in fragment order [tile][mfma][lane][8].
 // Row i of a 32-point tile carries label 32t + 16*((i>>2)&1) + 4*(i>>3) + (i&3).
-int ensure_frag(dm_constellation* c, int prec) {
-    if (c->d_frag[prec]) return DM_OK;
+int ensure_frag(dm_constellation* c, int prec, bool pad8) {
+    void*& frag_slot = pad8 ? c->d_frag8[prec] : c->d_frag[prec];
+    void*& pv_slot = pad8 ? c->d_pv8[prec] : c->d_pv[prec];
+    if (frag_slot) return DM_OK;
     const bool bf = (prec == DM_PREC_BF16 || prec == DM_PREC_BF16X3);
     const bool split = (prec == DM_PREC_BF16X3 || prec == DM_PREC_FP16X3);
-    const int D = c->D, M = c->M;
+    const int D = pad8 ? 8 : c->D, M = c->M, Dsrc = c->D;
     const int K = dm::mfma_slots(D, split), S = K / 16;
     auto hi = [&](float v) { return bf ? bf16_bits(v) : f16_bits(v); };
     auto val = [&](uint16_t b) { return bf ? bf16_value(b) : f16_value(b); };
     auto lo = [&](float v) { return hi(v - val(hi(v))); };
     std::vector<uint16_t> pv((size_t)M * K, 0);  // per label, K slots
     for (int l = 0; l < M; ++l) {
-        const float* x = &c->h_table[(size_t)l * D];
+        float x[32] = {0.0f};
+        for (int d = 0; d < Dsrc; ++d) x[d] = c->h_table[(size_t)l * Dsrc + d];
         double n = 0.0;
         for (int d = 0; d < D; ++d) n += (double)x[d] * (double)x[d];
         const float nn = -(float)n;
@@ -222,7 +203,7 @@ int ensure_frag(dm_constellation* c, int prec) {
                     fr[(((size_t)t * S + sidx) * 64 + ln) * 8 + v] = pv[(size_t)label * K + base + v];
             }
     void *d = nullptr, *dp = nullptr;
-    HIP_TRY(hipMalloc(&d, fr.size() * sizeof(uint16_t)));
+    DM_HIP_TRY(hipMalloc(&d, fr.size() * sizeof(uint16_t)));
     hipError_t e = hipMalloc(&dp, pv.size() * sizeof(uint16_t));
     if (e == hipSuccess) e = hipMemcpy(d, fr.data(), fr.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dp, pv.data(), pv.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
@@ -231,8 +212,19 @@ int ensure_frag(dm_constellation* c, int prec) {
         (void)hipFree(dp);
         return hip_fail(e, "fragment table upload");
     }
-    c->d_frag[prec] = d;
-    c->d_pv[prec] = dp;
+    frag_slot = d;
+    pv_slot = dp;
+    return DM_OK;
+}
+
+// FP32 label-order table with row stride 8 (batched launches).
+int ensure_table8(dm_constellation* c) {
+    if (c->d_table8) return DM_OK;
+    std::vector<float> t((size_t)c->M * 8, 0.0f);
+    for (int l = 0; l < c->M; ++l)
+        for (int d = 0; d < c->D; ++d) t[(size_t)l * 8 + d] = c->h_table[(size_t)l * c->D + d];
+    DM_HIP_TRY(hipMalloc(&c->d_table8, t.size() * sizeof(float)));
+    DM_HIP_TRY(hipMemcpy(c->d_table8, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
     return DM_OK;
 }
 
@@ -257,7 +249,7 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
                 if (exponent_scale(sigma2[s]) >= 30000.0f)
                     return fail(DM_EUNSUPPORTED, "sigma2 %g is too small for FP16 operands", sigma2[s]);
         }
-        int rr = ensure_frag(c, prec);
+        int rr = ensure_frag(c, prec, false);
         if (rr) return rr;
     }
     const int tile = prec == DM_PREC_FP32 ? dm::valu_tile_symbols() : dm::mfma_block_symbols();
@@ -278,29 +270,31 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
         a.snr[s].c = exponent_scale(sigma2[s]);
     }
     if (want_acc) {
-        HIP_TRY(hipMemsetAsync(c->d_acc, 0, sizeof(unsigned long long) * n_snr * dm::kAccSlots * 2, st));
-        HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
+        DM_HIP_TRY(hipMemsetAsync(c->d_acc, 0, sizeof(unsigned long long) * n_snr * dm::kAccSlots * 2, st));
+        DM_HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
     }
-    HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
+    DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
     const int grid = persistent_grid(c, tiles_per_snr * n_snr, prec == DM_PREC_FP32 ? 2 : 1);
     const int fix_grid = c->cus * 4;
     ProfRec pr{nullptr, nullptr, nullptr};
     if (g_prof_on) {
         pr = ProfRec{prof_event(), prof_event(), prof_event()};
-        if (pr.e0) HIP_TRY(hipEventRecord(pr.e0, st));
+        if (pr.e0) DM_HIP_TRY(hipEventRecord(pr.e0, st));
     }
-    if (prec == DM_PREC_FP32) HIP_TRY(dm::launch_demap_valu(a, grid, st));
-    else HIP_TRY(dm::launch_demap_mfma(a, prec, c->d_frag[prec], c->d_pv[prec], grid, st));
-    if (pr.e1) HIP_TRY(hipEventRecord(pr.e1, st));
-    HIP_TRY(dm::launch_fixup(a, fix_grid, st));
+    if (prec == DM_PREC_FP32) DM_HIP_TRY(dm::launch_demap_valu(a, grid, st));
+    else DM_HIP_TRY(dm::launch_demap_mfma(a, prec, c->d_frag[prec], c->d_pv[prec], grid, st));
+    if (pr.e1) DM_HIP_TRY(hipEventRecord(pr.e1, st));
+    DM_HIP_TRY(dm::launch_fixup(a, fix_grid, st));
     if (pr.e2) {
-        HIP_TRY(hipEventRecord(pr.e2, st));
+        DM_HIP_TRY(hipEventRecord(pr.e2, st));
         g_prof.push_back(pr);
     }
     return DM_OK;
 }
 
-}  // namespace
+}  // namespace dmapi
+
+using namespace dmapi;
 
 extern "C" {
 
@@ -376,6 +370,9 @@ void dm_constellation_destroy(dm_constellation* c) {
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     for (void* f : c->d_frag) (void)hipFree(f);
     for (void* f : c->d_pv) (void)hipFree(f);
+    for (void* f : c->d_frag8) (void)hipFree(f);
+    for (void* f : c->d_pv8) (void)hipFree(f);
+    (void)hipFree(c->d_table8);
     delete c;
 }
 
@@ -433,9 +430,9 @@ int dm_gmi_estimate(const dm_constellation* cc, int n_snr, const double* sigma2,
         if (r) return r;
         auto* acc = (unsigned long long*)c->h_stage;
         auto* fix = (uint32_t*)(acc + (size_t)dm::kMaxSnrPerLaunch * dm::kAccSlots * 2);
-        HIP_TRY(hipMemcpyAsync(acc, c->d_acc, sizeof(unsigned long long) * ns * dm::kAccSlots * 2, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(fix, c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        DM_HIP_TRY(hipMemcpyAsync(acc, c->d_acc, sizeof(unsigned long long) * ns * dm::kAccSlots * 2, hipMemcpyDeviceToHost, st));
+        DM_HIP_TRY(hipMemcpyAsync(fix, c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), hipMemcpyDeviceToHost, st));
+        DM_HIP_TRY(hipStreamSynchronize(st));
         if (fix[dm::kMaxSnrPerLaunch]) return fail(DM_EINVAL, "a transmitted index is >= M");
         for (int s = 0; s < ns; ++s) {
             long long gs = 0, ms = 0;  // two's-complement sums of the fixed-point slots
@@ -468,10 +465,10 @@ int dm_profile_enable(int on) {
 int dm_profile_read(double* main_ms, double* fixup_ms, int64_t* launches, int reset) {
     double a = 0.0, b = 0.0;
     for (auto& r : g_prof) {
-        HIP_TRY(hipEventSynchronize(r.e2));
+        DM_HIP_TRY(hipEventSynchronize(r.e2));
         float t1 = 0.0f, t2 = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t1, r.e0, r.e1));
-        HIP_TRY(hipEventElapsedTime(&t2, r.e1, r.e2));
+        DM_HIP_TRY(hipEventElapsedTime(&t1, r.e0, r.e1));
+        DM_HIP_TRY(hipEventElapsedTime(&t2, r.e1, r.e2));
         a += t1;
         b += t2;
     }

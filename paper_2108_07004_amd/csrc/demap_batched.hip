@@ -1,0 +1,172 @@
+// Batched exact demapping: one persistent launch over many (constellation, noise level, block)
+// instances of uneven M, D and N (gfx950).
+//
+// Work items are (instance, symbol tile) pairs listed instance by instance; the host cuts the
+// list into one contiguous, cost-balanced segment per workgroup, so a workgroup restages its
+// LDS table only when its segment crosses into the next instance.  Each instance runs either
+// the FP32 direct-difference body (one lane per symbol, 1024-symbol tiles) or the MFMA body
+// (one wave per 32 symbols, 512-symbol tiles), as chosen per (M, D) by the autotuner.  Batched
+// tables use a row stride of 8 (D <= 8 zero-padded): the padded coordinates contribute exact
+// zeros, and the MFMA operand vectors of every instance have the same K layout.
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "mfma_body.hpp"
+#include "valu_body.hpp"
+
+namespace dm {
+
+namespace {
+
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
+
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs a) {
+    extern __shared__ uint4 lds_raw[];
+    constexpr int S = Slots<8, SPLIT>::S;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int h = lane >> 5;
+    const int wave = tid >> 6;
+    const int wave_slot = (blockIdx.x * kWaves + wave) % kAccSlots;
+    const Sinks& k = a.sinks;
+    const int i0 = a.seg[blockIdx.x], i1 = a.seg[blockIdx.x + 1];
+    int staged = -1, cur = -1;
+    double gsum = 0.0, msum = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const WorkItem it = a.items[i];
+        const int inst = it.inst;
+        const BatchDesc& d = a.desc[inst];
+        const BlockView b = d.view;
+        const int kind = d.kind;
+        if (inst != staged) {  // restage the point table (whole block, uniform condition)
+            __syncthreads();
+            if (kind == kKindMfma) {
+                const int n16 = (b.M >> 5) * S * 64;
+                for (int j = tid; j < n16; j += kThreads) lds_raw[j] = d.frag[j];
+            } else {
+                float* lds = reinterpret_cast<float*>(lds_raw);
+                const int Mpad = b.M < 16 ? 16 : b.M;
+                for (int j = tid; j < Mpad * 8; j += kThreads)
+                    lds[j] = (j < b.M * 8) ? b.table[j] : 1.0e19f;  // padding rows: e_j = 0
+            }
+            __syncthreads();
+            staged = inst;
+        }
+        if (inst != cur) {
+            if (cur >= 0 && k.acc && lane == 0) {
+                acc_add(k.acc, cur, wave_slot, 0, gsum);
+                acc_add(k.acc, cur, wave_slot, 1, msum);
+            }
+            gsum = msum = 0.0;
+            cur = inst;
+        }
+        float g = 0.0f, mi = 0.0f;
+        bool active;
+        if (kind == kKindMfma) {
+            const int64_t n = it.n0 + wave * 32 + (lane & 31);
+            active = n < b.N;
+            float y[8];
+            load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
+            bool bad = false;
+            const Frags<T, S> bfr = build_symbol_frags<T, 8, SPLIT>(y, b.c, b.K, h, bad);
+            MfmaAcc A;
+            A.init();
+            mfma_tiles<T, 8, SPLIT>(lds_raw, lane, 0, b.M >> 5, b.m, bfr, A);
+            mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, lane, g, mi);
+        } else {
+            const int64_t n = it.n0 + tid;
+            active = n < b.N;
+            float y[8];
+            load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
+            DM_VALU_ACC_DECL
+            const int Mpad = b.M < 16 ? 16 : b.M;
+            valu_accumulate<8>(reinterpret_cast<const float*>(lds_raw), 0, Mpad, y, b.c, b.K, b.m, accA, accB, hi0,
+                               hi1);
+            valu_epilogue<8>(b, k, n, active, y, accA, accB, hi0, hi1, g, mi);
+        }
+        if (k.acc) {
+            gsum += wave_sum(active ? (double)g : 0.0);
+            msum += wave_sum(active ? (double)mi : 0.0);
+        }
+    }
+    if (cur >= 0 && k.acc && lane == 0) {
+        acc_add(k.acc, cur, wave_slot, 0, gsum);
+        acc_add(k.acc, cur, wave_slot, 1, msum);
+    }
+}
+
+// One wavefront per queued symbol of any instance.
+__global__ __launch_bounds__(256) void batched_fixup_kernel(const BatchArgs a) {
+    const Sinks& k = a.sinks;
+    const uint32_t count = min(*k.queue_count, k.queue_cap);
+    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * 4;
+    const int slot = (int)(wave % kAccSlots);
+    for (uint32_t i = wave; i < count; i += nwaves) {
+        const FixEntry e = k.queue[i];
+        const BlockView b = a.desc[e.tag].view;
+        double gc = 0.0, mc = 0.0;
+        fixup_wave<8>(b, k, e.n, e.mask, gc, mc);
+        if (k.acc && (threadIdx.x & 63) == 0) {
+            acc_add(k.acc, (int)e.tag, slot, 0, gc);
+            acc_add(k.acc, (int)e.tag, slot, 1, mc);
+        }
+    }
+}
+
+// Zero the accumulators and counters with a kernel (a graph must not hold memset nodes).
+__global__ void zero_words(uint32_t* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <typename T, bool SPLIT>
+hipError_t prepare_t() {
+    return hipFuncSetAttribute((const void*)demap_batched_kernel<T, SPLIT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kBatchedLdsBytes);
+}
+
+template <typename T, bool SPLIT>
+hipError_t launch_batched_t(const BatchArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((demap_batched_kernel<T, SPLIT>), dim3(grid), dim3(kThreads), kBatchedLdsBytes, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int batched_tile_symbols(int kind) { return kind == kKindMfma ? kWaves * 32 : kThreads; }
+
+hipError_t launch_demap_batched(const BatchArgs& a, int prec, int grid, hipStream_t st) {
+    switch (prec) {
+        case 0:  // FP32: every instance runs the VALU body; the MFMA operand type is unused
+        case 4: return launch_batched_t<_Float16, true>(a, grid, st);
+        case 1: return launch_batched_t<__bf16, false>(a, grid, st);
+        case 2: return launch_batched_t<_Float16, false>(a, grid, st);
+        case 3: return launch_batched_t<__bf16, true>(a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t prepare_batched(int prec) {
+    switch (prec) {
+        case 0:
+        case 4: return prepare_t<_Float16, true>();
+        case 1: return prepare_t<__bf16, false>();
+        case 2: return prepare_t<_Float16, false>();
+        case 3: return prepare_t<__bf16, true>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched_fixup(const BatchArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(batched_fixup_kernel, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(uint32_t* p, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace dm

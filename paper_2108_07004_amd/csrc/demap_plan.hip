@@ -1,0 +1,451 @@
+// Batched demapping plans: one persistent launch over many instances of uneven M, D and N,
+// an autotuner that picks the kernel body per (M, D, precision) class by timing, a
+// cost-balanced contiguous split of the work list over the workgroups, and a hipGraph that
+// replays zero-fill + batched kernel + fix-up with one launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/demap.h"
+#include "api_internal.hpp"
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+using namespace dmapi;
+
+namespace {
+
+constexpr int kProbeSymbols = 32768;  // symbols timed per autotune candidate
+
+struct TuneKey {
+    int M, D, prec, kind;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(M, D, prec, kind) < std::tie(o.M, o.D, o.prec, o.kind);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, double> g_tune;  // ns per (symbol, point) pair
+bool g_tune_loaded = false;
+
+std::string tune_cache_path() {
+    const char* p = std::getenv("DM_AUTOTUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Cache file: one line per entry, "arch M D prec kind ns_per_pair".
+void load_tune_cache() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    std::ifstream f(path);
+    std::string arch = arch_name(), a;
+    TuneKey k;
+    double v;
+    while (f >> a >> k.M >> k.D >> k.prec >> k.kind >> v)
+        if (a == arch && v > 0.0) g_tune[k] = v;
+}
+
+void save_tune_cache() {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    std::ofstream f(path, std::ios::trunc);
+    const std::string arch = arch_name();
+    for (const auto& kv : g_tune)
+        f << arch << ' ' << kv.first.M << ' ' << kv.first.D << ' ' << kv.first.prec << ' ' << kv.first.kind << ' '
+          << kv.second << '\n';
+}
+
+bool mfma_possible(const dm_constellation* c, int prec) {
+    if (prec == DM_PREC_FP32 || c->M < 32 || c->D > 8) return false;
+    const bool split = (prec == DM_PREC_BF16X3 || prec == DM_PREC_FP16X3);
+    const int S = dm::mfma_slots(8, split) / 16;
+    return (size_t)(c->M / 32) * S * 1024 <= (size_t)dm::kBatchedLdsBytes;
+}
+
+}  // namespace
+
+struct dm_plan {
+    int n_inst = 0, prec = 0, grid = 0, fix_grid = 0, device = 0;
+    std::vector<dm_instance> inst;
+    std::vector<int> kind;
+    std::vector<double> ns_per_pair;
+    dm::BatchDesc* d_desc = nullptr;
+    dm::WorkItem* d_items = nullptr;
+    int32_t* d_seg = nullptr;
+    uint32_t* d_words = nullptr;  // acc (2 words per int64) | fix_pairs[n] | bad_tx | queue_count
+    size_t n_words = 0;
+    dm::FixEntry* d_queue = nullptr;
+    uint32_t queue_cap = 0;
+    void* h_stage = nullptr;
+    dm::BatchArgs args{};
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int build_descs(dm_plan* p, std::vector<dm::BatchDesc>& desc) {
+    desc.resize(p->n_inst);
+    for (int i = 0; i < p->n_inst; ++i) {
+        const dm_instance& in = p->inst[i];
+        dm_constellation* c = const_cast<dm_constellation*>(in.c);
+        int r = ensure_table8(c);
+        if (r) return r;
+        dm::BatchDesc& d = desc[i];
+        std::memset(&d, 0, sizeof d);
+        d.view.table = c->d_table8;
+        d.view.row2label = c->d_row2label;
+        d.view.tx = in.tx;
+        d.view.y = in.y;
+        d.view.llr = in.llr;
+        d.view.N = in.N;
+        d.view.M = c->M;
+        d.view.D = c->D;
+        d.view.m = c->m;
+        d.view.c = exponent_scale(in.sigma2);
+        d.view.K = (float)(123 - c->m);
+        d.view.flag_thresh = std::ldexp(1.0f, c->m - 102);
+        d.view.near_thresh = std::ldexp(1.0f, c->m - 42);
+        d.view.want_llr = in.llr ? 1 : 0;
+        d.view.tag = i;
+        d.kind = p->kind[i];
+        if (d.kind == dm::kKindMfma) {
+            r = ensure_frag(c, p->prec, true);
+            if (r) return r;
+            d.frag = (const uint4*)c->d_frag8[p->prec];
+            d.pv = (const uint16_t*)c->d_pv8[p->prec];
+        }
+    }
+    return DM_OK;
+}
+
+// Work list in instance order and its contiguous split into `grid` cost-balanced segments.
+void build_work(const dm_plan* p, std::vector<dm::WorkItem>& items, std::vector<int32_t>& seg, int grid) {
+    std::vector<double> cost;
+    for (int i = 0; i < p->n_inst; ++i) {
+        const int tile = dm::batched_tile_symbols(p->kind[i]);
+        const double per = p->ns_per_pair[i] * p->inst[i].c->M;
+        for (int64_t n0 = 0; n0 < p->inst[i].N; n0 += tile) {
+            items.push_back(dm::WorkItem{i, 0, n0});
+            cost.push_back(per * (double)std::min<int64_t>(tile, p->inst[i].N - n0));
+        }
+    }
+    double total = 0.0;
+    for (double v : cost) total += v;
+    seg.assign(grid + 1, (int32_t)items.size());
+    seg[0] = 0;
+    double acc = 0.0;
+    int g = 1;
+    for (size_t j = 0; j < items.size() && g < grid; ++j) {
+        acc += cost[j];
+        while (g < grid && acc >= total * g / grid) seg[g++] = (int32_t)(j + 1);
+    }
+}
+
+int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const std::vector<dm::WorkItem>& items,
+                       const std::vector<int32_t>& seg) {
+    DM_HIP_TRY(hipMalloc(&p->d_desc, desc.size() * sizeof(dm::BatchDesc)));
+    DM_HIP_TRY(hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(dm::WorkItem)));
+    DM_HIP_TRY(hipMalloc(&p->d_seg, seg.size() * sizeof(int32_t)));
+    DM_HIP_TRY(hipMemcpy(p->d_desc, desc.data(), desc.size() * sizeof(dm::BatchDesc), hipMemcpyHostToDevice));
+    if (!items.empty())
+        DM_HIP_TRY(hipMemcpy(p->d_items, items.data(), items.size() * sizeof(dm::WorkItem), hipMemcpyHostToDevice));
+    DM_HIP_TRY(hipMemcpy(p->d_seg, seg.data(), seg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    p->n_words = (size_t)p->n_inst * dm::kAccSlots * 2 * 2 + p->n_inst + 2;
+    DM_HIP_TRY(hipMalloc(&p->d_words, p->n_words * sizeof(uint32_t)));
+    int64_t total_n = 0;
+    for (const auto& in : p->inst) total_n += in.N;
+    p->queue_cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(total_n, 1024), 1 << 22);
+    DM_HIP_TRY(hipMalloc(&p->d_queue, (size_t)p->queue_cap * sizeof(dm::FixEntry)));
+    DM_HIP_TRY(hipHostMalloc(&p->h_stage, p->n_words * sizeof(uint32_t), hipHostMallocDefault));
+    auto* acc = reinterpret_cast<unsigned long long*>(p->d_words);
+    uint32_t* tail = p->d_words + (size_t)p->n_inst * dm::kAccSlots * 2 * 2;
+    p->args.desc = p->d_desc;
+    p->args.items = p->d_items;
+    p->args.seg = p->d_seg;
+    p->args.sinks.acc = acc;
+    p->args.sinks.fix_pairs = tail;
+    p->args.sinks.bad_tx = tail + p->n_inst;
+    p->args.sinks.queue_count = tail + p->n_inst + 1;
+    p->args.sinks.queue = p->d_queue;
+    p->args.sinks.queue_cap = p->queue_cap;
+    return DM_OK;
+}
+
+int enqueue(dm_plan* p, hipStream_t st) {
+    DM_HIP_TRY(dm::launch_zero_words(p->d_words, p->n_words, st));
+    DM_HIP_TRY(dm::launch_demap_batched(p->args, p->prec, p->grid, st));
+    DM_HIP_TRY(dm::launch_batched_fixup(p->args, p->fix_grid, st));
+    return DM_OK;
+}
+
+void free_plan(dm_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    (void)hipFree(p->d_desc);
+    (void)hipFree(p->d_items);
+    (void)hipFree(p->d_seg);
+    (void)hipFree(p->d_words);
+    (void)hipFree(p->d_queue);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    delete p;
+}
+
+// Plan skeleton without graph: validated instances, kinds and per-pair costs set by caller.
+int make_plan(const dm_instance* inst, int n_inst, int prec, const std::vector<int>& kinds,
+              const std::vector<double>& cost, int grid_cap, dm_plan** out) {
+    auto* p = new (std::nothrow) dm_plan();
+    if (!p) return fail(DM_ENOMEM, "host allocation failed");
+    p->n_inst = n_inst;
+    p->prec = prec;
+    p->inst.assign(inst, inst + n_inst);
+    p->kind = kinds;
+    p->ns_per_pair = cost;
+    int cus = 0;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "device query");
+    }
+    std::vector<dm::BatchDesc> desc;
+    std::vector<dm::WorkItem> items;
+    std::vector<int32_t> seg;
+    int r = build_descs(p, desc);
+    if (r) {
+        free_plan(p);
+        return r;
+    }
+    p->grid = std::max(1, grid_cap > 0 ? std::min(grid_cap, cus) : cus);
+    e = dm::prepare_batched(prec);  // LDS attribute set outside any graph capture
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "hipFuncSetAttribute(batched kernel)");
+    }
+    p->fix_grid = cus * 4;
+    build_work(p, items, seg, p->grid);
+    r = alloc_plan_buffers(p, desc, items, seg);
+    if (r) {
+        free_plan(p);
+        return r;
+    }
+    *out = p;
+    return DM_OK;
+}
+
+int validate_instances(const dm_instance* inst, int n_inst, int prec) {
+    if (!inst || n_inst < 1) return fail(DM_EINVAL, "need at least one instance");
+    if (prec < DM_PREC_FP32 || prec > DM_PREC_FP16X3) return fail(DM_EINVAL, "unknown precision %d", prec);
+    int dev = -1;
+    DM_HIP_TRY(hipGetDevice(&dev));
+    for (int i = 0; i < n_inst; ++i) {
+        const dm_instance& in = inst[i];
+        if (!in.c) return fail(DM_EINVAL, "instance %d has no constellation", i);
+        if (in.c->device != dev) return fail(DM_EINVAL, "instance %d lives on another device", i);
+        if (in.c->D > 8) return fail(DM_EUNSUPPORTED, "batched plans support D <= 8 (instance %d has D=%d)", i, in.c->D);
+        if ((size_t)std::max(16, in.c->M) * 8 * 4 > (size_t)dm::kBatchedLdsBytes)
+            return fail(DM_EUNSUPPORTED, "instance %d: M=%d exceeds the batched table size", i, in.c->M);
+        if (in.N < 0 || in.N >= (int64_t(1) << 31)) return fail(DM_EINVAL, "instance %d: bad N", i);
+        int r = validate_sigma2(in.sigma2);
+        if (r) return r;
+        if (in.N > 0) {
+            if ((r = check_device_ptr(in.y, "instance y", dev))) return r;
+            if (in.tx && (r = check_device_ptr(in.tx, "instance tx", dev))) return r;
+            if (in.llr && (r = check_device_ptr(in.llr, "instance llr", dev))) return r;
+        }
+        if ((prec == DM_PREC_FP16 || prec == DM_PREC_FP16X3) && mfma_possible(in.c, prec) &&
+            (in.c->max_norm >= 60000.0f || exponent_scale(in.sigma2) >= 30000.0f))
+            return fail(DM_EUNSUPPORTED, "instance %d is outside the FP16 operand range", i);
+    }
+    return DM_OK;
+}
+
+// Time one instance class with one kind on the first kProbeSymbols symbols of its block.
+int time_candidate(const dm_instance& in, int prec, int kind, double* ns_per_pair) {
+    dm_instance probe = in;
+    probe.N = std::min<int64_t>(in.N, kProbeSymbols);
+    probe.llr = nullptr;  // timing run writes no LLRs
+    dm_plan* p = nullptr;
+    int r = make_plan(&probe, 1, prec, std::vector<int>{kind}, std::vector<double>{1.0}, 0, &p);
+    if (r) return r;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best = 1e30f;
+    for (int rep = 0; e == hipSuccess && rep < 3; ++rep) {
+        (void)hipEventRecord(e0, st);
+        if ((r = enqueue(p, st))) break;
+        (void)hipEventRecord(e1, st);
+        e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) best = std::min(best, ms);  // first run warms up
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    free_plan(p);
+    if (r) return r;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    *ns_per_pair = (double)best * 1e6 / ((double)std::max<int64_t>(probe.N, 1) * in.c->M);
+    return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dm_plan_create(const dm_instance* inst, int n_inst, int prec, int flags, dm_plan** out) {
+    if (!out) return fail(DM_EINVAL, "null plan pointer");
+    *out = nullptr;
+    int r = validate_instances(inst, n_inst, prec);
+    if (r) return r;
+    std::vector<int> kinds(n_inst);
+    std::vector<double> cost(n_inst, 0.0);
+    for (int i = 0; i < n_inst; ++i) {
+        const dm_constellation* c = inst[i].c;
+        const bool can_mfma = mfma_possible(c, prec);
+        if (flags & DM_PLAN_FORCE_VALU) {
+            kinds[i] = dm::kKindValu;
+        } else if (flags & DM_PLAN_FORCE_MFMA) {
+            if (!can_mfma) return fail(DM_EUNSUPPORTED, "instance %d cannot use the MFMA body", i);
+            kinds[i] = dm::kKindMfma;
+        } else {
+            kinds[i] = can_mfma ? dm::kKindMfma : dm::kKindValu;
+        }
+        // Default cost model: measured-order-of-magnitude ns per pair of each body.
+        cost[i] = kinds[i] == dm::kKindMfma ? 1.6e-4 : 5.0e-4;
+    }
+    if ((flags & DM_PLAN_AUTOTUNE) && !(flags & (DM_PLAN_FORCE_VALU | DM_PLAN_FORCE_MFMA))) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        load_tune_cache();
+        bool tuned = false;
+        for (int i = 0; i < n_inst; ++i) {
+            const dm_constellation* c = inst[i].c;
+            if (inst[i].N == 0) continue;
+            double best = 0.0;
+            int best_kind = dm::kKindValu;
+            for (int kind = dm::kKindValu; kind <= dm::kKindMfma; ++kind) {
+                if (kind == dm::kKindMfma && !mfma_possible(c, prec)) continue;
+                const TuneKey key{c->M, c->D, prec, kind};
+                auto it = g_tune.find(key);
+                double ns;
+                if (it != g_tune.end()) {
+                    ns = it->second;
+                } else {
+                    r = time_candidate(inst[i], prec, kind, &ns);
+                    if (r) return r;
+                    g_tune[key] = ns;
+                    tuned = true;
+                }
+                if (best == 0.0 || ns < best) {
+                    best = ns;
+                    best_kind = kind;
+                }
+            }
+            kinds[i] = best_kind;
+            cost[i] = best;
+        }
+        if (tuned) save_tune_cache();
+    }
+    dm_plan* p = nullptr;
+    r = make_plan(inst, n_inst, prec, kinds, cost, 0, &p);
+    if (r) return r;
+    // Capture zero-fill + batched kernel + fix-up into a graph on a private stream.
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        r = enqueue(p, p->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+        p->graph = g;
+        if (!r && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && !r) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (r || e != hipSuccess) {
+        free_plan(p);
+        return r ? r : hip_fail(e, "graph capture");
+    }
+    *out = p;
+    return DM_OK;
+}
+
+int dm_plan_launch(dm_plan* p, void* stream) {
+    if (!p) return fail(DM_EINVAL, "null plan");
+    DM_HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return DM_OK;
+}
+
+int dm_plan_results(dm_plan* p, double* gmi, double* mi, int64_t* fixup_pairs, void* stream) {
+    if (!p || !gmi) return fail(DM_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    DM_HIP_TRY(hipMemcpyAsync(p->h_stage, p->d_words, p->n_words * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    DM_HIP_TRY(hipStreamSynchronize(st));
+    const auto* acc = reinterpret_cast<const unsigned long long*>(p->h_stage);
+    const auto* tail = reinterpret_cast<const uint32_t*>(p->h_stage) + (size_t)p->n_inst * dm::kAccSlots * 2 * 2;
+    if (tail[p->n_inst]) return fail(DM_EINVAL, "a transmitted index is >= M");
+    for (int i = 0; i < p->n_inst; ++i) {
+        long long gs = 0, ms = 0;
+        for (int k = 0; k < dm::kAccSlots; ++k) {
+            gs += (long long)acc[((size_t)i * dm::kAccSlots + k) * 2 + 0];
+            ms += (long long)acc[((size_t)i * dm::kAccSlots + k) * 2 + 1];
+        }
+        const double N = (double)p->inst[i].N;
+        const bool has = p->inst[i].tx && p->inst[i].N > 0;
+        gmi[i] = has ? (double)gs / dm::kFixScale / N : NAN;
+        if (mi) mi[i] = has ? (double)ms / dm::kFixScale / N : NAN;
+        if (fixup_pairs) fixup_pairs[i] = tail[i];
+    }
+    return DM_OK;
+}
+
+int dm_plan_info(const dm_plan* p, int* kinds, double* ns_per_pair) {
+    if (!p) return fail(DM_EINVAL, "null plan");
+    for (int i = 0; i < p->n_inst; ++i) {
+        if (kinds) kinds[i] = p->kind[i];
+        if (ns_per_pair) ns_per_pair[i] = p->ns_per_pair[i];
+    }
+    return DM_OK;
+}
+
+void dm_plan_destroy(dm_plan* p) { free_plan(p); }
+
+int dm_demap_batched(const dm_instance* inst, int n_inst, int prec, int flags, double* gmi, double* mi,
+                     void* stream) {
+    dm_plan* p = nullptr;
+    int r = dm_plan_create(inst, n_inst, prec, flags, &p);
+    if (r) return r;
+    r = dm_plan_launch(p, stream);
+    if (!r) r = dm_plan_results(p, gmi, mi, nullptr, stream);
+    dm_plan_destroy(p);
+    return r;
+}
+
+}  // extern "C"

@@ -66,6 +66,32 @@ struct LaunchArgs {
     SnrArg snr[kMaxSnrPerLaunch];
 };
 
+// ---- batched launch over many instances ----
+constexpr int kKindValu = 0;  // FP32 direct-difference body
+constexpr int kKindMfma = 1;  // MFMA cross-term body
+constexpr int kBatchedLdsBytes = 131072;
+
+struct BatchDesc {             // one instance (device memory); view.tag = instance index
+    BlockView view;            // table: FP32 label order with row stride 8
+    const uint4* frag;         // MFMA point operands, fragment order (D padded to 8), or null
+    const uint16_t* pv;        // the same operands per label, or null
+    int32_t kind;
+    int32_t pad;
+};
+
+struct WorkItem {              // symbols [n0, n0 + tile) of one instance
+    int32_t inst;
+    int32_t pad;
+    int64_t n0;
+};
+
+struct BatchArgs {
+    const BatchDesc* desc;
+    const WorkItem* items;
+    const int32_t* seg;        // workgroup g processes items [seg[g], seg[g+1])
+    Sinks sinks;
+};
+
 __device__ __forceinline__ BlockView view_snr(const LaunchArgs& a, int s) {
     BlockView v;
     v.table = a.table;

@@ -29,4 +29,20 @@ int mfma_block_symbols();
 // operands per label ([label][K slots], 16-bit), read for the transmitted points.
 hipError_t launch_demap_mfma(const LaunchArgs& a, int prec, const void* frag, const void* pv, int grid, hipStream_t st);
 
+// Symbols per work item of the batched kernel for an instance kind (kKindValu / kKindMfma).
+int batched_tile_symbols(int kind);
+
+// Allow the batched kernel of a precision its 128 KiB of dynamic LDS (call before launching or
+// capturing it).
+hipError_t prepare_batched(int prec);
+
+// Persistent batched kernel (prec selects the MFMA operand variant used by MFMA instances).
+hipError_t launch_demap_batched(const BatchArgs& a, int prec, int grid, hipStream_t st);
+
+// Fix-up of queued symbols of any instance (tables with row stride 8).
+hipError_t launch_batched_fixup(const BatchArgs& a, int grid, hipStream_t st);
+
+// p[0..n) = 0 with a kernel (usable inside a captured graph).
+hipError_t launch_zero_words(uint32_t* p, size_t n, hipStream_t st);
+
 }  // namespace dm

@@ -1,0 +1,129 @@
+"""Batched plans: one persistent launch over uneven instances, autotuned bodies, hipGraph replay.
+
+Every instance is checked against the FP64 oracle (GMI / MI within 1e-4 bit, LLRs element-wise
+with the bound of the body that ran it); graph replays are interleaved with unrelated eager GPU
+work and synchronisations and each replay is compared with the first.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2108_07004_amd as dm
+import workloads as W
+from gpu_helpers import GMI_TOL, LLR_TOL_FP32, rel_err
+
+pytestmark = pytest.mark.gpu
+
+LLR_TOL_MFMA_FP16X3 = 1e-3  # up to 20 dB on dense constellations (see the MFMA precision tests)
+
+
+def _build(instances, device="cuda:0", with_llr=True):
+    import torch
+    items, host = [], []
+    consts = {}
+    for inst in instances:
+        key = id(inst.const)
+        if key not in consts:
+            consts[key] = dm.Constellation(inst.const.points, inst.const.labels)
+        c = consts[key]
+        tx, z = inst.tx_noise()
+        y = W.awgn(inst.const.points, tx, z, inst.sigma2)
+        y_t = torch.from_numpy(y).to(device)
+        tx_t = torch.from_numpy(tx.view(np.int16)).to(device)
+        llr = torch.full((inst.N, inst.const.m), float("nan"), dtype=torch.float32, device=device) if with_llr else None
+        items.append((c, inst.sigma2, y_t, tx_t, llr))
+        host.append((inst, y, tx))
+    return items, host, consts
+
+
+def _small_instances():
+    return W.batched_instances(64, n_lo=7, n_hi=10)
+
+
+def test_batched_plan_matches_oracle_per_instance():
+    import torch
+    insts = _small_instances()
+    items, host, _ = _build(insts)
+    plan = dm.Plan(items, prec="fp16x3", autotune=True)
+    kinds, ns = plan.info()
+    assert set(kinds.tolist()) <= {0, 1} and np.all(ns > 0)
+    plan.launch()
+    gmi, mi, fx = plan.results()
+    torch.cuda.synchronize()
+    for i, (inst, y, tx) in enumerate(host):
+        ref = oracle.demap(inst.const.points, inst.const.labels, inst.sigma2, y, tx)
+        got = items[i][4].cpu().numpy()
+        tol = LLR_TOL_FP32 if kinds[i] == 0 else LLR_TOL_MFMA_FP16X3
+        e = rel_err(got, ref["llr"])
+        assert e <= tol, (i, inst.const.M, inst.const.D, inst.snr_db, int(kinds[i]), e)
+        assert abs(gmi[i] - ref["gmi"]) <= GMI_TOL, (i, gmi[i], ref["gmi"])
+        assert abs(mi[i] - ref["mi_mean"]) <= GMI_TOL, (i, mi[i], ref["mi_mean"])
+
+
+def test_forced_bodies_agree():
+    insts = [i for i in _small_instances() if i.const.M >= 32][:16]
+    items, host, _ = _build(insts, with_llr=False)
+    pv = dm.Plan(items, prec="fp16x3", force="valu")
+    pm = dm.Plan(items, prec="fp16x3", force="mfma")
+    assert np.all(pv.info()[0] == 0) and np.all(pm.info()[0] == 1)
+    pv.launch()
+    gv, mv, _ = pv.results()
+    pm.launch()
+    gm, mm, _ = pm.results()
+    assert np.max(np.abs(gv - gm)) <= GMI_TOL and np.max(np.abs(mv - mm)) <= GMI_TOL
+    for i, (inst, y, tx) in enumerate(host):
+        ref = oracle.demap(inst.const.points, inst.const.labels, inst.sigma2, y, tx, llr=False)
+        assert abs(gv[i] - ref["gmi"]) <= GMI_TOL
+
+
+def test_graph_replays_interleaved_with_eager_work():
+    import torch
+    insts = _small_instances()[:24]
+    items, host, _ = _build(insts)
+    plan = dm.Plan(items, prec="bf16x3", autotune=False)
+    plan.launch()
+    g0, m0, f0 = plan.results()
+    l0 = [it[4].clone() for it in items]
+    scratch = torch.randn(1 << 20, device="cuda:0")
+    for rep in range(4):
+        for it in items:
+            it[4].fill_(float("nan"))
+        scratch = (scratch * 1.0001).sin_()  # unrelated eager kernels between replays
+        s = float(scratch.sum())
+        torch.cuda.synchronize()
+        plan.launch()
+        g, m, f = plan.results()
+        assert np.array_equal(g, g0) and np.array_equal(m, m0) and np.array_equal(f, f0), rep
+        for a, b in zip(l0, items):
+            assert torch.equal(a, b[4]), rep
+        assert np.isfinite(s)
+
+
+def test_empty_and_gmi_free_instances():
+    import torch
+    insts = _small_instances()[:4]
+    items, host, _ = _build(insts)
+    c = items[0][0]
+    e = torch.empty((0, c.D), dtype=torch.float32, device="cuda:0")
+    items.append((c, 0.1, e, torch.empty(0, dtype=torch.int16, device="cuda:0"), None))
+    items.append((items[1][0], items[1][1], items[1][2], None, None))
+    g, mi = dm.demap_batched(items, prec="fp16x3")
+    assert np.isnan(g[4]) and np.isnan(g[5]) and np.isnan(mi[5])
+    for i in range(4):
+        inst, y, tx = host[i]
+        ref = oracle.demap(inst.const.points, inst.const.labels, inst.sigma2, y, tx, llr=False)
+        assert abs(g[i] - ref["gmi"]) <= GMI_TOL
+
+
+def test_plan_rejects_unsupported():
+    import torch
+    g = W.rng(53, "misc", 0)
+    c9 = dm.Constellation(g.standard_normal((64, 9)).astype(np.float32), np.arange(64, dtype=np.uint16))
+    y = torch.zeros((8, 9), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(dm.DemapError):
+        dm.Plan([(c9, 0.1, y, None, None)])
+    c4 = dm.Constellation(W.dp_qpsk().points, W.dp_qpsk().labels)
+    with pytest.raises(dm.DemapError):
+        dm.Plan([(c4, 0.1, torch.zeros((8, 4), dtype=torch.float32, device="cuda:0"), None, None)], force="mfma")

@@ -246,3 +246,41 @@ def mlp_init_weights(D: int, H: int, m: int, config: int = 4) -> dict:
         w["W" + name] = g.uniform(-b, b, (fi, fo)).astype(np.float32)
         w["b" + name] = np.zeros(fo, dtype=np.float32)
     return w
+
+
+@dataclass(frozen=True)
+class Instance:
+    """One batched instance: constellation, SNR, block size and its own tx / noise streams."""
+    index: int
+    const: Constellation
+    N: int
+    snr_db: float
+
+    @property
+    def sigma2(self) -> float:
+        return float(sigma2_from_snr_db(self.snr_db))
+
+    def tx_noise(self, N: int | None = None):
+        n = self.N if N is None else N
+        return tx_indices(self.const.M, n, 3, self.index), unit_noise(n, self.const.D, 3, self.index)
+
+
+def batched_instances(count: int = 64, n_lo: int = 14, n_hi: int = 22) -> list:
+    """Uneven instances: M in {16,64,256,1024,2048}, D in {2,4,8}, N log-uniform in
+    [2^n_lo, 2^n_hi], SNR uniform in [0, 20] dB; Gaussian constellations as the 8D recipe,
+    except (M, D) = (16, 4) -> DP-QPSK and (256, 4) -> DP-16QAM."""
+    g = rng(3, "instances")
+    out = []
+    for i in range(count):
+        M = int(g.choice([16, 64, 256, 1024, 2048]))
+        D = int(g.choice([2, 4, 8]))
+        N = int(round(2.0 ** g.uniform(n_lo, n_hi)))
+        snr = float(g.uniform(0.0, 20.0))
+        if (M, D) == (16, 4):
+            c = dp_qpsk()
+        elif (M, D) == (256, 4):
+            c = dp_16qam()
+        else:
+            c = gaussian_constellation(M, D, 3, i)
+        out.append(Instance(i, c, N, snr))
+    return out
