@@ -99,6 +99,63 @@ def bench_batched(prec, steps, warmup):
             "fixup_pairs": int(np.sum(fx)), "prec": prec}
 
 
+MLP_FLOP_PER_SYMBOL = 2 * (9 * 256 + 256 * 256 + 256 * 11)  # (8+1) -> 256 -> 256 -> 11 multiply-adds x 2
+MFMA_BF16_PEAK = 2.5e15  # MI355X dense BF16 MFMA, FLOP/s
+
+
+def bench_learned(const, w, ys, tx_t, llrs, exact_gmi, exact_sym_per_s, exact_prec, n_train, batch, steps):
+    """Train the learned demapper on n_train exact-LLR samples over U[0,15] dB, then time learned
+    demapping of the headline block (audit on 1/64 + exact fallback per SNR) against the exact path."""
+    import torch
+
+    import paper_2108_07004_amd as dm
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    y_tr, s2_tr = W.mlp_samples_torch(w.const.points, n_train, 0.0, 15.0, dev)
+    torch.cuda.synchronize()
+    net = dm.MLP(const, W.mlp_init_weights(w.const.D, 256, w.const.m))
+    t0 = time.perf_counter()
+    train_loss = net.train(const, y_tr, s2_tr, batch=batch, epochs=1, lr=2e-3, lr_final=2e-5, target_prec="fp32",
+                           snr_range=(0.0, 15.0))
+    t_train = time.perf_counter() - t0
+    del y_tr, s2_tr
+    log(f"learned: trained on {n_train} samples in {t_train:.1f} s, final loss {train_loss:.4g}")
+
+    res = None
+    dm.demap_learned(net, const, w.sigma2, ys, tx_t, llrs, exact_prec=exact_prec)  # warm-up (packs weights)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = dm.demap_learned(net, const, w.sigma2, ys, tx_t, llrs, exact_prec=exact_prec)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    gmi, loss_est, fb = res
+    n_sym = w.N * len(w.sigma2)
+    # the network alone (no audit, every point learned): its kernel's MFMA roofline
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g_net, _, _ = dm.demap_learned(net, const, w.sigma2, ys, tx_t, llrs, max_gmi_loss=-1.0)
+    torch.cuda.synchronize()
+    dt_net = (time.perf_counter() - t0) / steps
+    flops = float(n_sym) * MLP_FLOP_PER_SYMBOL
+    return {
+        "workload": f"train: {n_train} samples U[0,15] dB, batch {batch}, 1 epoch, Adam 2e-3 -> 2e-5 cosine; "
+                    f"infer: {w.name} N={w.N} x {len(w.sigma2)} SNR with LLRs, audit 1/64, exact fallback ({exact_prec})",
+        "train_s": t_train, "train_samples_per_s": n_train / t_train, "train_final_loss": train_loss,
+        "symbols_per_s": n_sym / dt, "ms_per_step": dt * 1e3, "speedup_vs_exact": (n_sym / dt) / exact_sym_per_s,
+        "fallback": [dm.FALLBACK[int(v)] for v in fb],
+        "audit_gmi_loss": [None if not np.isfinite(v) else round(float(v), 5) for v in loss_est],
+        "gmi": [round(float(v), 6) for v in gmi],
+        "gmi_loss_vs_exact": [round(float(a - b), 6) for a, b in zip(exact_gmi, gmi)],
+        "network_only": {"symbols_per_s": n_sym / dt_net, "ms_per_step": dt_net * 1e3,
+                         "gmi_loss_vs_exact": [round(float(a - b), 5) for a, b in zip(exact_gmi, g_net)],
+                         "roofline": {"bound": "mfma", "achieved": flops / dt_net / 1e12,
+                                      "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                                      "frac": flops / dt_net / MFMA_BF16_PEAK, "traffic": None}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +166,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=131072, help="oracle symbols per SNR point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip training + timing the learned demapper")
+    ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
+    ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -203,6 +263,12 @@ def main():
         out["batched"] = bench_batched(args.prec if args.prec != "fp32" else "fp16x3", max(3, args.steps), 2)
         log(f"batched: {out['batched']['ms_per_launch']:.3f} ms/launch, "
             f"{out['batched']['symbols_per_s'] / 1e9:.3f} Gsym/s")
+    if not args.no_learned and w.name == "gauss8d2048":
+        log("learned: training on the GPU, then learned vs exact demapping")
+        out["learned"] = bench_learned(const, w, ys, tx_t, llrs, gmi, value, args.prec, args.learned_train,
+                                       args.learned_batch, max(2, min(args.steps, 5)))
+        log(f"learned: {out['learned']['symbols_per_s'] / 1e9:.3f} Gsym/s "
+            f"({out['learned']['speedup_vs_exact']:.2f}x exact), fallback {out['learned']['fallback']}")
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w, tx, z, args.cpu_sample)

@@ -150,6 +150,117 @@ void dm_plan_destroy(dm_plan* plan);
 int dm_demap_batched(const dm_instance* inst, int n_inst, int prec, int flags, double* gmi, double* mi,
                      void* stream);
 
+/*
+ * Exact LLRs with one noise variance per symbol (the learned demapper's training targets are
+ * drawn at continuously distributed SNRs; also usable for fading channels).
+ *   sigma2  DEVICE, N FP32 per-symbol variances.  Entries that are not finite and > 0 give
+ *           non-finite LLRs for their symbols (never a fault).
+ *   prec    DM_PREC_FP32, DM_PREC_BF16 or DM_PREC_BF16X3 (the FP16 operand range depends on
+ *           1/sigma2, which the host cannot bound without reading the array).
+ * Enqueued on `stream`; does not synchronise.  Errors: as dm_demap_llr.
+ */
+int dm_demap_llr_var(const dm_constellation* c, const float* sigma2, const float* y, int64_t N, float* llr,
+                     int prec, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Learned demapper.  The paper replaces nothing by a network; it names learned (neural-
+ * network) demapping among the receiver's future directions (Sec. 6).  The network here is an
+ * MLP (D+1) -> 256 -> 256 -> m with tanh-form GELU, BF16 weights and activations and FP32
+ * accumulation, whose m outputs estimate the exact LLRs (nats).  Its inputs are y and the SNR
+ * feature (s - 7.5) / 7.5 with s = -10 log10(2 sigma2), the SNR in dB of a constellation with
+ * unit energy per two real dimensions.  Training minimises the soft binary cross-entropy
+ * between sigmoid(output) and sigmoid(exact LLR), averaged over samples and bits, with Adam on
+ * FP32 master weights.  A network is bound to the constellation it was created for.
+ *
+ * Weight arrays (HOST, FP32, dm_mlp_param_count(D, m) values) are ordered
+ *   W1 [(D+1) x 256] row-major (out = x W + b), b1 [256], W2 [256 x 256], b2 [256],
+ *   W3 [256 x m], b3 [m].
+ * ---------------------------------------------------------------------------------------- */
+typedef struct dm_mlp dm_mlp;
+
+/* (D+1)*256 + 256 + 256*256 + 256 + 256*m + m, or DM_EINVAL unless 1 <= D <= 13 and 1 <= m <= 32. */
+int64_t dm_mlp_param_count(int32_t D, int32_t m);
+
+/*
+ * Create a network for constellation c with the given initial weights (HOST, copied).  Its
+ * trained SNR range starts unbounded; dm_mlp_train sets it.
+ * Errors: DM_EINVAL (null, non-finite weight), DM_EUNSUPPORTED (D > 13 or m > 32), DM_ENOMEM, DM_EHIP.
+ */
+int dm_mlp_create(const dm_constellation* c, const float* weights, dm_mlp** out);
+void dm_mlp_destroy(dm_mlp* net);
+/* FP32 master weights to HOST `weights` (synchronises the device). */
+int dm_mlp_get_weights(const dm_mlp* net, float* weights);
+/* Replace the weights (HOST) and reset the Adam state (synchronises the device). */
+int dm_mlp_set_weights(dm_mlp* net, const float* weights);
+/* Adam steps taken and the trained SNR range in dB (any output may be NULL). */
+int dm_mlp_info(const dm_mlp* net, int64_t* steps, double* snr_lo_db, double* snr_hi_db);
+
+typedef struct dm_train_config {
+    int32_t batch;             /* samples per Adam step: a multiple of 256 in [256, 65536] */
+    int32_t epochs;            /* passes over the samples, >= 1 */
+    float lr, lr_final;        /* cosine decay from lr (first step) to lr_final (last step) */
+    float beta1, beta2, eps;   /* Adam; a value <= 0 selects 0.9, 0.999, 1e-8 */
+    int32_t target_prec;       /* exact-target precision: DM_PREC_FP32, DM_PREC_BF16 or DM_PREC_BF16X3 */
+    double snr_lo_db, snr_hi_db;  /* SNR range (s above) the samples cover; becomes the trained range */
+} dm_train_config;
+
+/*
+ * Train on N samples.  y DEVICE N x D received symbols, sigma2 DEVICE N FP32 noise variance of
+ * each sample.  The exact LLRs of each sample under its own sigma2 (computed with c, chunk by
+ * chunk) are the targets; batches are taken in order; the last N % batch samples of each epoch
+ * are not used.  loss (HOST, may be NULL): mean loss over the last min(64, steps) steps.
+ * Synchronises `stream`.  Errors: DM_EINVAL (bad config, N < batch, another constellation),
+ * DM_EUNSUPPORTED, DM_ENOMEM, DM_EHIP.
+ */
+int dm_mlp_train(dm_mlp* net, const dm_constellation* c, const dm_train_config* cfg, const float* y,
+                 const float* sigma2, int64_t N, double* loss, void* stream);
+
+/*
+ * Loss gradients at the current weights for one batch of B samples (a multiple of 256) with
+ * given targets, without updating anything: y DEVICE B x D, sigma2 DEVICE B FP32, target
+ * DEVICE B x m FP32 (nats).  grads HOST (weight order above), loss HOST or NULL.
+ * Synchronises `stream`.
+ */
+int dm_mlp_gradients(dm_mlp* net, const float* y, const float* sigma2, const float* target, int32_t B,
+                     float* grads, double* loss, void* stream);
+
+typedef struct dm_learned_opts {
+    double max_gmi_loss;  /* bits per symbol; an audited point whose estimated GMI loss exceeds
+                             this is recomputed exactly.  < 0 disables the audit. */
+    int32_t audit_log2;   /* the audit covers the first max(ceil(N / 2^audit_log2), 8192) symbols */
+    int32_t exact_prec;   /* DM_PREC_* of the audit and of every exact fallback */
+} dm_learned_opts;  /* NULL selects {0.01, 6, DM_PREC_FP32} */
+
+enum {
+    DM_LEARNED_OK = 0,             /* the network's LLRs and GMI are returned */
+    DM_FALLBACK_AUDIT = 1,         /* audit loss above the bound: exact results returned */
+    DM_FALLBACK_SNR = 2,           /* SNR outside the trained range: exact results returned */
+    DM_FALLBACK_CONSTELLATION = 3  /* c is not the network's constellation: exact results returned */
+};
+
+/*
+ * Learned demapping of one transmitted block at n_snr noise levels (same arguments as
+ * dm_gmi_estimate, tx and llr optional).  Per point: if the network covers it, its LLRs are
+ * written and, with tx, its GMI is estimated; the audit then runs the exact path on the
+ * block's prefix and estimates the GMI loss as exact minus learned GMI over that prefix.  Points
+ * that fail a check are recomputed exactly over the whole block (LLRs overwritten).
+ *   gmi            HOST n_snr (required with tx; NaN for N == 0).
+ *   gmi_loss       HOST n_snr or NULL: the audit's loss estimate (NaN when not audited).
+ *   used_fallback  HOST n_snr: DM_LEARNED_OK or the DM_FALLBACK_* reason.
+ * Synchronises `stream`.  Errors: as dm_gmi_estimate.
+ */
+int dm_demap_learned(dm_mlp* net, const dm_constellation* c, int n_snr, const double* sigma2,
+                     const float* const* y, const uint16_t* tx, int64_t N, float* const* llr,
+                     const dm_learned_opts* opts, double* gmi, double* gmi_loss, int* used_fallback,
+                     void* stream);
+
+/* Checkpoint: weights, Adam state, step count, trained SNR range and constellation identity in
+ * a little-endian binary file with a versioned header. */
+int dm_mlp_save(const dm_mlp* net, const char* path);
+/* Load a checkpoint for constellation c (same D and m required; the recorded identity is kept,
+ * so a different table makes dm_demap_learned fall back). */
+int dm_mlp_load(const dm_constellation* c, const char* path, dm_mlp** out);
+
 /* Number of (symbol, bit) pairs that the last call on this thread sent through the
  * far-subset underflow fix-up, per SNR point (HOST array of n_snr, may be NULL).
  * Returns the total, or a negative DM_E* if no call has run on this thread. */

@@ -92,3 +92,46 @@ def adam_step(w, g, state, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
         mhat = m_ / (1.0 - beta1 ** step)
         vhat = v_ / (1.0 - beta2 ** step)
         w[k] -= lr * mhat / (np.sqrt(vhat) + eps)
+
+
+# ---- storage rounding of the mixed-precision network (BF16 operands, FP32 accumulation) ----
+
+def bf16_round(x):
+    """Round to the nearest BF16 value (ties to even), via FP32, returned as float64."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def identity(x):
+    return np.asarray(x, dtype=np.float64)
+
+
+def forward_stored(w, X, rnd=bf16_round, b1=None):
+    """Forward pass where every stored operand is rounded by `rnd`: the weights, the inputs and
+    the two hidden activations after GELU (accumulation and biases in full precision).  `b1`
+    overrides the first-layer bias (e.g. its BF16 hi + lo pair).  Returns (out, cache)."""
+    Xr = rnd(X)
+    h1 = Xr @ rnd(w["W1"]) + (w["b1"] if b1 is None else b1)
+    a1 = rnd(gelu(h1))
+    h2 = a1 @ rnd(w["W2"]) + w["b2"]
+    a2 = rnd(gelu(h2))
+    out = a2 @ rnd(w["W3"]) + w["b3"]
+    return out, (Xr, h1, a1, h2, a2)
+
+
+def backward_stored(w, cache, out, llr_target, rnd=bf16_round):
+    """Gradients of `loss` with the stored back-propagated deltas rounded by `rnd` (the output
+    delta and the two hidden deltas), weights rounded as in forward_stored."""
+    X, h1, a1, h2, a2 = cache
+    B, m = out.shape
+    d_out = rnd((sigmoid(out) - sigmoid(llr_target)) / (B * m))
+    g = {"W3": a2.T @ d_out, "b3": d_out.sum(axis=0)}
+    d_h2 = rnd((d_out @ rnd(w["W3"]).T) * gelu_grad(h2))
+    g["W2"] = a1.T @ d_h2
+    g["b2"] = d_h2.sum(axis=0)
+    d_h1 = rnd((d_h2 @ rnd(w["W2"]).T) * gelu_grad(h1))
+    g["W1"] = X.T @ d_h1
+    g["b1"] = d_h1.sum(axis=0)
+    return g

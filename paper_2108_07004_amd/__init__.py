@@ -16,8 +16,9 @@ from typing import Sequence
 
 import numpy as np
 
-__all__ = ["Constellation", "DemapError", "PREC", "Plan", "demap_batched", "demap_llr", "gmi_estimate",
-           "last_fixup_count", "library_path", "load_library", "probe_valu_rates", "profile_enable", "profile_read"]
+__all__ = ["Constellation", "DemapError", "MLP", "PREC", "Plan", "demap_batched", "demap_learned", "demap_llr",
+           "demap_llr_var", "gmi_estimate", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
+           "probe_valu_rates", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}
@@ -73,6 +74,30 @@ def load_library():
     lib.dm_plan_destroy.restype = None
     lib.dm_demap_batched.argtypes = [P, I, I, I, P, P, P]
     lib.dm_demap_batched.restype = I
+    lib.dm_demap_llr_var.argtypes = [P, P, P, I64, P, I, P]
+    lib.dm_demap_llr_var.restype = I
+    lib.dm_mlp_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.dm_mlp_param_count.restype = I64
+    lib.dm_mlp_create.argtypes = [P, P, ctypes.POINTER(P)]
+    lib.dm_mlp_create.restype = I
+    lib.dm_mlp_destroy.argtypes = [P]
+    lib.dm_mlp_destroy.restype = None
+    lib.dm_mlp_get_weights.argtypes = [P, P]
+    lib.dm_mlp_get_weights.restype = I
+    lib.dm_mlp_set_weights.argtypes = [P, P]
+    lib.dm_mlp_set_weights.restype = I
+    lib.dm_mlp_info.argtypes = [P, P, P, P]
+    lib.dm_mlp_info.restype = I
+    lib.dm_mlp_train.argtypes = [P, P, P, P, P, I64, P, P]
+    lib.dm_mlp_train.restype = I
+    lib.dm_mlp_gradients.argtypes = [P, P, P, P, ctypes.c_int32, P, P, P]
+    lib.dm_mlp_gradients.restype = I
+    lib.dm_demap_learned.argtypes = [P, P, I, P, P, P, I64, P, P, P, P, P, P]
+    lib.dm_demap_learned.restype = I
+    lib.dm_mlp_save.argtypes = [P, ctypes.c_char_p]
+    lib.dm_mlp_save.restype = I
+    lib.dm_mlp_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P)]
+    lib.dm_mlp_load.restype = I
     lib.dm_last_error.restype = ctypes.c_char_p
     lib.dm_version.restype = ctypes.c_char_p
     _lib = lib
@@ -292,3 +317,172 @@ def demap_batched(items, prec: str = "fp16x3", autotune: bool = False, stream=No
                                            PLAN_AUTOTUNE if autotune else 0, g.ctypes.data_as(ctypes.c_void_p),
                                            mi.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)))
     return g, mi
+
+
+def demap_llr_var(const: Constellation, sigma2, y, llr=None, prec: str = "fp32", stream=None):
+    """Exact LLRs with one noise variance per symbol (sigma2: (N,) FP32 tensor) — dm_demap_llr_var."""
+    import torch
+    N = int(y.shape[0])
+    yp = _dev_tensor(y, ("float32",), (N, const.D), "y")
+    sp = _dev_tensor(sigma2, ("float32",), (N,), "sigma2")
+    if llr is None:
+        llr = torch.empty((N, const.m), dtype=torch.float32, device=y.device)
+    lp = _dev_tensor(llr, ("float32",), (N, const.m), "llr")
+    _check(load_library().dm_demap_llr_var(const.handle, sp, yp, N, lp, PREC[prec], _stream_handle(stream)))
+    return llr
+
+
+_MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+MLP_HIDDEN = 256
+
+FALLBACK = {0: "learned", 1: "audit", 2: "snr_range", 3: "constellation"}
+
+
+def mlp_param_count(D: int, m: int) -> int:
+    n = int(load_library().dm_mlp_param_count(D, m))
+    if n < 0:
+        _check(n)
+    return n
+
+
+def _mlp_shapes(D: int, m: int):
+    H = MLP_HIDDEN
+    return {"W1": (D + 1, H), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (H, m), "b3": (m,)}
+
+
+def _flatten(w: dict, D: int, m: int) -> np.ndarray:
+    parts = []
+    for k, shp in _mlp_shapes(D, m).items():
+        a = np.asarray(w[k], dtype=np.float32)
+        if a.shape != shp:
+            raise ValueError(f"{k} has shape {a.shape}, expected {shp}")
+        parts.append(a.reshape(-1))
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+def _unflatten(flat: np.ndarray, D: int, m: int) -> dict:
+    out, o = {}, 0
+    for k, shp in _mlp_shapes(D, m).items():
+        n = int(np.prod(shp))
+        out[k] = flat[o:o + n].reshape(shp).copy()
+        o += n
+    return out
+
+
+class _TrainConfig(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("target_prec", ctypes.c_int32), ("snr_lo_db", ctypes.c_double),
+                ("snr_hi_db", ctypes.c_double)]
+
+
+class _LearnedOpts(ctypes.Structure):
+    _fields_ = [("max_gmi_loss", ctypes.c_double), ("audit_log2", ctypes.c_int32), ("exact_prec", ctypes.c_int32)]
+
+
+class MLP:
+    """Learned demapper network bound to one constellation (dm_mlp_*).
+
+    Weights are dicts of FP32 arrays W1 (D+1, 256), b1, W2 (256, 256), b2, W3 (256, m), b3 with
+    out = x @ W + b.
+    """
+
+    def __init__(self, const: Constellation, weights: dict | None = None, _handle=None):
+        self.D, self.m = const.D, const.m
+        if _handle is not None:
+            self._h = _handle
+            return
+        flat = _flatten(weights, self.D, self.m)
+        h = ctypes.c_void_p()
+        _check(load_library().dm_mlp_create(const.handle, flat.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def load(cls, const: Constellation, path: str) -> "MLP":
+        h = ctypes.c_void_p()
+        _check(load_library().dm_mlp_load(const.handle, str(path).encode(), ctypes.byref(h)))
+        return cls(const, _handle=h)
+
+    def save(self, path: str):
+        _check(load_library().dm_mlp_save(self._h, str(path).encode()))
+
+    def get_weights(self) -> dict:
+        flat = np.empty(mlp_param_count(self.D, self.m), dtype=np.float32)
+        _check(load_library().dm_mlp_get_weights(self._h, flat.ctypes.data_as(ctypes.c_void_p)))
+        return _unflatten(flat, self.D, self.m)
+
+    def set_weights(self, weights: dict):
+        flat = _flatten(weights, self.D, self.m)
+        _check(load_library().dm_mlp_set_weights(self._h, flat.ctypes.data_as(ctypes.c_void_p)))
+
+    def info(self):
+        st = ctypes.c_int64()
+        lo = ctypes.c_double()
+        hi = ctypes.c_double()
+        _check(load_library().dm_mlp_info(self._h, ctypes.byref(st), ctypes.byref(lo), ctypes.byref(hi)))
+        return {"steps": st.value, "snr_lo_db": lo.value, "snr_hi_db": hi.value}
+
+    def train(self, const: Constellation, y, sigma2, batch: int = 4096, epochs: int = 1, lr: float = 1e-3,
+              lr_final: float = 1e-5, target_prec: str = "fp32", snr_range=(0.0, 15.0), beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, stream=None) -> float:
+        """Train on y (N x D) with per-sample noise variances sigma2 (N,) FP32; returns the final mean loss."""
+        N = int(y.shape[0])
+        yp = _dev_tensor(y, ("float32",), (N, self.D), "y")
+        sp = _dev_tensor(sigma2, ("float32",), (N,), "sigma2")
+        cfg = _TrainConfig(batch, epochs, lr, lr_final, beta1, beta2, eps, PREC[target_prec], float(snr_range[0]),
+                           float(snr_range[1]))
+        loss = ctypes.c_double()
+        _check(load_library().dm_mlp_train(self._h, const.handle, ctypes.byref(cfg), yp, sp, N, ctypes.byref(loss),
+                                           _stream_handle(stream)))
+        return loss.value
+
+    def gradients(self, y, sigma2, target, stream=None):
+        """(gradients dict, loss) of one batch at the current weights (dm_mlp_gradients)."""
+        B = int(y.shape[0])
+        yp = _dev_tensor(y, ("float32",), (B, self.D), "y")
+        sp = _dev_tensor(sigma2, ("float32",), (B,), "sigma2")
+        tp = _dev_tensor(target, ("float32",), (B, self.m), "target")
+        flat = np.empty(mlp_param_count(self.D, self.m), dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(load_library().dm_mlp_gradients(self._h, yp, sp, tp, B, flat.ctypes.data_as(ctypes.c_void_p),
+                                               ctypes.byref(loss), _stream_handle(stream)))
+        return _unflatten(flat, self.D, self.m), loss.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().dm_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def demap_learned(net: MLP, const: Constellation, sigma2: Sequence[float], ys, tx=None, llrs=None,
+                  max_gmi_loss: float = 0.01, audit_log2: int = 6, exact_prec: str = "fp32", stream=None):
+    """Learned demapping with exact audit / fallback (dm_demap_learned).
+
+    Returns (gmi, gmi_loss, used_fallback) NumPy arrays; used_fallback codes are in FALLBACK.
+    """
+    s2 = np.ascontiguousarray(np.asarray(sigma2, dtype=np.float64).reshape(-1))
+    ns = int(s2.shape[0])
+    ylist = [ys[i] for i in range(ns)]
+    N = int(ylist[0].shape[0])
+    yptr = (ctypes.c_void_p * ns)(*[_dev_tensor(t, ("float32",), (N, const.D), "y[s]").value for t in ylist])
+    txp = None if tx is None else _dev_tensor(tx, ("int16", "uint16"), (N,), "tx")
+    lptr = None
+    if llrs is not None:
+        lptr = (ctypes.c_void_p * ns)(*[_dev_tensor(llrs[i], ("float32",), (N, const.m), "llr[s]").value
+                                        for i in range(ns)])
+    gmi = np.full(ns, np.nan)
+    loss = np.full(ns, np.nan)
+    fb = np.zeros(ns, dtype=np.int32)
+    opts = _LearnedOpts(max_gmi_loss, audit_log2, PREC[exact_prec])
+    _check(load_library().dm_demap_learned(
+        net._h, const.handle, ns, s2.ctypes.data_as(ctypes.c_void_p), ctypes.cast(yptr, ctypes.c_void_p), txp, N,
+        None if lptr is None else ctypes.cast(lptr, ctypes.c_void_p), ctypes.byref(opts),
+        gmi.ctypes.data_as(ctypes.c_void_p), loss.ctypes.data_as(ctypes.c_void_p), fb.ctypes.data_as(ctypes.c_void_p),
+        _stream_handle(stream)))
+    return gmi, loss, fb

@@ -5,6 +5,8 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
@@ -17,7 +19,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 VALU ops stay off: plain float code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -35,15 +36,27 @@ def sources() -> list[Path]:
     return sorted(CSRC.glob("*.hip"))
 
 
-def build(verbose: bool = False) -> Path:
-    """Compile every HIP source into paper_2108_07004_amd/libdemap.so (always recompiles)."""
-    tmp = LIB.with_name(f"libdemap.so.tmp{os.getpid()}")
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", str(tmp), *map(str, sources())]
+def _run(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{res.stderr[-6000:]}")
+        raise RuntimeError(f"hipcc failed ({res.returncode}): {' '.join(cmd)}\n{res.stderr[-6000:]}")
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> Path:
+    """Compile every HIP source (in parallel, one object each) and link
+    paper_2108_07004_amd/libdemap.so; always recompiles."""
+    cc = hipcc()
+    srcs = sources()
+    jobs = jobs or max(1, min(len(srcs), 8, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="demap_build_") as d:
+        objs = [Path(d) / (s.stem + ".o") for s in srcs]
+        with ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(lambda so: _run([cc, *HIPCC_FLAGS, "-c", str(so[0]), "-o", str(so[1])], verbose),
+                        zip(srcs, objs)))
+        tmp = LIB.with_name(f"libdemap.so.tmp{os.getpid()}")
+        _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -29,6 +29,7 @@ struct dm_constellation {
     void* d_frag8[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     void* d_pv8[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     float max_norm = 0.0f;                // max ||x||^2 (FP16 operand range check)
+    uint64_t hash = 0;                    // identity of (M, D, label-order table)
     std::mutex mu;
 };
 
@@ -36,6 +37,7 @@ namespace dmapi {
 
 // Record a message for dm_last_error() and return `code`.
 int fail(int code, const char* fmt, ...);
+void clear_error();
 int hip_fail(hipError_t e, const char* what);
 
 int check_device_ptr(const void* p, const char* name, int device);
@@ -46,6 +48,18 @@ float exponent_scale(double sigma2);
 // MFMA point-operand tables of a precision (pad8: row layout padded to D = 8).
 int ensure_frag(dm_constellation* c, int prec, bool pad8);
 int ensure_table8(dm_constellation* c);
+
+// Exact path over up to 32 SNR points of one block (scratch of c; caller holds c->mu).
+// sigma2_sym, when not null, gives each symbol its own noise variance (sigma2 is then unused).
+int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
+              int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st, const float* sigma2_sym);
+// Exact GMI / MI (and LLRs) of n_snr points, synchronising `st`; arguments already validated.
+int gmi_run(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
+            int64_t N, float* const* llr, double* gmi, double* mi, int prec, hipStream_t st);
+// Exact LLRs with per-symbol noise variances (device FP32, N); arguments already validated.
+int llr_var_run(dm_constellation* c, const float* sigma2_sym, const float* y, int64_t N, float* llr, int prec,
+                hipStream_t st);
+uint64_t table_hash(int M, int D, const std::vector<float>& table);
 
 }  // namespace dmapi
 

@@ -45,6 +45,8 @@ hipEvent_t prof_event() {
     return e;
 }
 
+void clear_error() { g_err.clear(); }
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -239,7 +241,7 @@ int validate_sigma2(double s2) {
 
 // Run the demapper over up to kMaxSnrPerLaunch SNR points of one block.
 int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
-              int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st) {
+              int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st, const float* sigma2_sym) {
     if (prec != DM_PREC_FP32) {
         if (c->D > 8) return fail(DM_EUNSUPPORTED, "MFMA precisions support D <= 8 (D=%d)", c->D);
         if (c->M < 32) return fail(DM_EUNSUPPORTED, "MFMA precisions need M >= 32 (M=%d)", c->M);
@@ -261,6 +263,7 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
     a.tiles_per_snr = tiles_per_snr;
     a.n_snr = n_snr;
     a.want_llr = llr ? 1 : 0;
+    a.sigma2_sym = sigma2_sym;
     a.sinks.acc = want_acc ? c->d_acc : nullptr;
     a.sinks.fix_pairs = want_acc ? c->d_fix_pairs : nullptr;
     a.sinks.bad_tx = want_acc ? c->d_fix_pairs + dm::kMaxSnrPerLaunch : nullptr;
@@ -290,6 +293,31 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
         g_prof.push_back(pr);
     }
     return DM_OK;
+}
+
+int llr_var_run(dm_constellation* c, const float* sigma2_sym, const float* y, int64_t N, float* llr, int prec,
+                hipStream_t st) {
+    std::lock_guard<std::mutex> lock(c->mu);
+    const double unit = 1.0;  // replaced per symbol by sigma2_sym
+    const float* ys[1] = {y};
+    float* ls[1] = {llr};
+    return run_chunk(c, 1, &unit, ys, nullptr, N, ls, false, prec, st, sigma2_sym);
+}
+
+// FNV-1a over M, D and the label-order table: identifies the constellation a network was trained on.
+uint64_t table_hash(int M, int D, const std::vector<float>& table) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(&M, sizeof M);
+    mix(&D, sizeof D);
+    mix(table.data(), table.size() * sizeof(float));
+    return h;
 }
 
 }  // namespace dmapi
@@ -348,6 +376,7 @@ int dm_constellation_create(const float* points, const uint16_t* labels, int32_t
             c->h_table[(size_t)l * D + d] = points[(size_t)row_of[l] * D + d];
             padded[(size_t)l * c->DP + d] = points[(size_t)row_of[l] * D + d];
         }
+    c->hash = table_hash(M, D, c->h_table);
     if ((e = hipMalloc(&c->d_table, padded.size() * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&c->d_row2label, M * sizeof(uint16_t))) != hipSuccess ||
         (e = hipMemcpy(c->d_table, padded.data(), padded.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -392,7 +421,7 @@ int dm_demap_llr(const dm_constellation* cc, double sigma2, const float* y, int6
     std::lock_guard<std::mutex> lock(c->mu);
     const float* ys[1] = {y};
     float* ls[1] = {llr};
-    return run_chunk(c, 1, &sigma2, ys, nullptr, N, ls, false, prec, (hipStream_t)stream);
+    return run_chunk(c, 1, &sigma2, ys, nullptr, N, ls, false, prec, (hipStream_t)stream, nullptr);
 }
 
 int dm_gmi_estimate(const dm_constellation* cc, int n_snr, const double* sigma2, const float* const* y,
@@ -422,11 +451,20 @@ int dm_gmi_estimate(const dm_constellation* cc, int n_snr, const double* sigma2,
         if ((r = check_device_ptr(y[s], "y[s]", c->device))) return r;
         if (llr && (r = check_device_ptr(llr[s], "llr[s]", c->device))) return r;
     }
+    return gmi_run(c, n_snr, sigma2, y, tx, N, llr, gmi, mi, prec, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace dmapi {
+
+int gmi_run(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
+            int64_t N, float* const* llr, double* gmi, double* mi, int prec, hipStream_t st) {
+    int r;
     std::lock_guard<std::mutex> lock(c->mu);
-    hipStream_t st = (hipStream_t)stream;
     for (int s0 = 0; s0 < n_snr; s0 += dm::kMaxSnrPerLaunch) {
         const int ns = std::min(dm::kMaxSnrPerLaunch, n_snr - s0);
-        r = run_chunk(c, ns, sigma2 + s0, y + s0, tx, N, llr ? llr + s0 : nullptr, true, prec, st);
+        r = run_chunk(c, ns, sigma2 + s0, y + s0, tx, N, llr ? llr + s0 : nullptr, true, prec, st, nullptr);
         if (r) return r;
         auto* acc = (unsigned long long*)c->h_stage;
         auto* fix = (uint32_t*)(acc + (size_t)dm::kMaxSnrPerLaunch * dm::kAccSlots * 2);
@@ -442,10 +480,31 @@ int dm_gmi_estimate(const dm_constellation* cc, int n_snr, const double* sigma2,
             }
             gmi[s0 + s] = (double)gs / dm::kFixScale / (double)N;
             if (mi) mi[s0 + s] = (double)ms / dm::kFixScale / (double)N;
-            g_fix_counts[s0 + s] = fix[s];
+            if ((size_t)(s0 + s) < g_fix_counts.size()) g_fix_counts[s0 + s] = fix[s];
         }
     }
     return DM_OK;
+}
+
+}  // namespace dmapi
+
+extern "C" {
+
+int dm_demap_llr_var(const dm_constellation* cc, const float* sigma2, const float* y, int64_t N, float* llr,
+                     int prec, void* stream) {
+    g_err.clear();
+    auto* c = const_cast<dm_constellation*>(cc);
+    if (!c) return fail(DM_EINVAL, "constellation is null");
+    if (N < 0 || N >= (int64_t(1) << 31)) return fail(DM_EINVAL, "N=%lld out of range", (long long)N);
+    if (prec != DM_PREC_FP32 && prec != DM_PREC_BF16 && prec != DM_PREC_BF16X3)
+        return fail(DM_EUNSUPPORTED, "per-symbol noise variances need an FP32-range precision (FP32, BF16, BF16X3)");
+    if (N == 0) return DM_OK;
+    int r;
+    if ((r = check_current_device(c))) return r;
+    if ((r = check_device_ptr(sigma2, "sigma2", c->device))) return r;
+    if ((r = check_device_ptr(y, "y", c->device))) return r;
+    if ((r = check_device_ptr(llr, "llr", c->device))) return r;
+    return llr_var_run(c, sigma2, y, N, llr, prec, (hipStream_t)stream);
 }
 
 int dm_profile_enable(int on) {

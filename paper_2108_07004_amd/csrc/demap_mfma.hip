@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
             gsum = msum = 0.0;
             cur = s_idx;
         }
-        const BlockView b = view_snr(a, s_idx);
         const bool active = n < a.N;
+        const BlockView b = view_sym(a, s_idx, n, active);
         float y[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) y[d] = active ? b.y[(size_t)n * D + d] : 0.0f;

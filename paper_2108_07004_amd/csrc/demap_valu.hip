@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kValuThreads) void demap_valu_kernel(const LaunchAr
             gsum = msum = 0.0;
             cur = s;
         }
-        const BlockView b = view_snr(a, s);
         const bool active = n < a.N;
+        const BlockView b = view_sym(a, s, n, active);
         float y[DP];
         load_symbol<DP>(y, b.y + (size_t)(active ? n : 0) * D, D, active);
 
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a) {
     const int slot = (int)(wave % kAccSlots);
     for (uint32_t i = wave; i < count; i += nwaves) {
         const FixEntry e = k.queue[i];
-        const BlockView b = view_snr(a, (int)e.tag);
+        const BlockView b = view_sym(a, (int)e.tag, e.n, true);
         double gc = 0.0, mc = 0.0;
         fixup_wave<DP>(b, k, e.n, e.mask, gc, mc);
         if (k.acc && (threadIdx.x & 63) == 0) {

@@ -62,6 +62,7 @@ struct LaunchArgs {
     int32_t M, D, m, n_snr;
     float K, flag_thresh, near_thresh;
     int32_t want_llr;
+    const float* sigma2_sym;     // per-symbol noise variances (overrides snr[].c), or null
     Sinks sinks;
     SnrArg snr[kMaxSnrPerLaunch];
 };
@@ -109,6 +110,13 @@ __device__ __forceinline__ BlockView view_snr(const LaunchArgs& a, int s) {
     v.near_thresh = a.near_thresh;
     v.want_llr = a.want_llr;
     v.tag = s;
+    return v;
+}
+
+// View of SNR block s as seen by symbol n (per-symbol noise variance when given).
+__device__ __forceinline__ BlockView view_sym(const LaunchArgs& a, int s, int64_t n, bool active) {
+    BlockView v = view_snr(a, s);
+    if (a.sigma2_sym) v.c = 0.72134752044448170f / (active ? a.sigma2_sym[n] : 1.0f);  // log2(e) / (2 sigma2)
     return v;
 }
 

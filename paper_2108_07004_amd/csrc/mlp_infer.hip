@@ -1,0 +1,188 @@
+// Fused inference of the learned demapper (gfx950): all BF16 weights (152 KiB of MFMA operand
+// fragments + FP32 biases) live in LDS; each wavefront runs 32 received symbols through the
+// three layers on v_mfma_f32_32x32x16_bf16 and writes LLRs and per-symbol GMI terms.
+//
+// Hidden units are permuted so that no activation has to move between lanes: the A operand
+// of output block b (32 units) has in row i the unit
+//     u(b, i) = 32 b + 16 (r / 8) + 8 h + (r % 8),  r = 4 (i / 8) + (i % 4),  h = (i / 4) % 2,
+// so the MFMA result register r of a lane in half h holds unit 32 b + 16 (r / 8) + 8 h + (r % 8)
+// of its symbol (column l % 32) — exactly the 8 K-slots that lane supplies as the B operand of
+// the next layer's K-steps 2b (r < 8) and 2b + 1 (r >= 8).  Layer 2's output block b is
+// consumed at once by layer 3's K-steps 2b and 2b + 1, so only layer 1's 16 operand fragments
+// stay live.  Layer 1's bias rides in feature slots 14 and 15 (constant 1) as a BF16 hi/lo
+// pair, ~16 significant bits; b2 and b3 sit in LDS in the permuted order, FP32.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "mlp_kernels.hpp"
+
+namespace dm {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int kH = 256;
+constexpr int kThreads = 512;   // 8 waves; one block per CU (the weights fill the LDS)
+constexpr int kW1Frags = 8 * 64;        // [block][lane]
+constexpr int kW2Frags = 8 * 16 * 64;   // [block][kstep][lane]
+constexpr int kW3Frags = 16 * 64;       // [kstep][lane]
+constexpr int kFrags = kW1Frags + kW2Frags + kW3Frags;
+constexpr int kBiasFloats = 8 * 2 * 16 + 2 * 16;  // b2 in [block][h][r] order, b3 in [h][r] order
+constexpr int kLdsBytes = kFrags * 16 + kBiasFloats * 4;
+
+__device__ __forceinline__ int perm_unit(int b, int i) {
+    const int r = 4 * (i >> 3) + (i & 3);
+    const int h = (i >> 2) & 1;
+    return 32 * b + 16 * (r >> 3) + 8 * h + (r & 7);
+}
+
+// tanh-form GELU, 0.5 x (1 + tanh(u)) = x / (1 + exp(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3)
+__device__ __forceinline__ float gelu_f(float x) {
+    const float u2 = 1.5957691216057308f * x * fmaf(0.044715f, x * x, 1.0f);
+    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * u2));
+}
+
+// Fragment table from row-major (out x in) BF16 weights: W1t [256 x 32] (inputs 0..13 used),
+// W2t [256 x 256], W3t [32 x 256]; the FP32 layer-1 bias b1 becomes input columns 14 (hi) and
+// 15 (lo).  One thread per fragment.
+__global__ void pack_kernel(const __bf16* W1t, const __bf16* W2t, const __bf16* W3t, const float* b1, uint4* frag) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= kFrags) return;
+    __bf16 v[8];
+    if (f < kW1Frags) {
+        const int b = f / 64, l = f % 64;
+        const int u = perm_unit(b, l % 32);
+        const __bf16 hi = (__bf16)b1[u];
+        const __bf16 lo = (__bf16)(b1[u] - (float)hi);
+        for (int q = 0; q < 8; ++q) {
+            const int k = 8 * (l / 32) + q;
+            v[q] = k == 14 ? hi : (k == 15 ? lo : W1t[u * 32 + k]);
+        }
+    } else if (f < kW1Frags + kW2Frags) {
+        const int g = f - kW1Frags;
+        const int b = g / (16 * 64), t = (g / 64) % 16, l = g % 64;
+        const int u = perm_unit(b, l % 32);
+        for (int q = 0; q < 8; ++q) v[q] = W2t[u * kH + 16 * t + 8 * (l / 32) + q];
+    } else {
+        const int g = f - kW1Frags - kW2Frags;
+        const int t = g / 64, l = g % 64;
+        const int o = l % 32;
+        for (int q = 0; q < 8; ++q) v[q] = W3t[o * kH + 16 * t + 8 * (l / 32) + q];
+    }
+    frag[f] = *reinterpret_cast<const uint4*>(v);
+}
+
+__global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs a) {
+    extern __shared__ uint4 lds[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, j = lane & 31;
+    float* lbias = reinterpret_cast<float*>(lds + kFrags);
+    for (int i = tid; i < kFrags; i += kThreads) lds[i] = a.frag[i];
+    // b2 as [block][h][r]: unit 32b + 16(r/8) + 8h + (r%8); b3 as [h][r]: output 8(r/4) + 4h + (r%4)
+    for (int i = tid; i < 8 * 2 * 16; i += kThreads) {
+        const int b = i / 32, hh = (i / 16) % 2, r = i % 16;
+        lbias[i] = a.bias[kH + 32 * b + 16 * (r >> 3) + 8 * hh + (r & 7)];
+    }
+    for (int i = tid; i < 32; i += kThreads) {
+        const int hh = i / 16, r = i % 16;
+        lbias[8 * 2 * 16 + i] = a.bias[2 * kH + 8 * (r >> 2) + 4 * hh + (r & 3)];
+    }
+    __syncthreads();
+    const uint4* w1 = lds;
+    const uint4* w2 = lds + kW1Frags;
+    const uint4* w3 = lds + kW1Frags + kW2Frags;
+
+    const int64_t tiles = (a.N + 31) / 32;
+    const int slot = (blockIdx.x * (kThreads / 64) + wave) % kAccSlots;
+    double gsum = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave; t < tiles; t += (int64_t)gridDim.x * (kThreads / 64)) {
+        const int64_t n = t * 32 + j;
+        const bool active = n < a.N;
+        // features: slot k = 8h + q; k < D: y, k == D: SNR feature, k = 14, 15: 1 (bias), else 0
+        bf16x8 xf;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = 8 * h + q;
+            float v = 0.0f;
+            if (k < a.D) v = active ? a.y[(size_t)n * a.D + k] : 0.0f;
+            else if (k == a.D) v = a.snr_feature;
+            else if (k >= 14) v = 1.0f;
+            xf[q] = (__bf16)v;
+        }
+        bf16x8 a1[16];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, w1[b * 64 + lane]), xf, f32x16{}, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) a1[2 * b + (r >> 3)][r & 7] = (__bf16)gelu_f(acc[r]);
+        }
+        f32x16 acc3 = {};
+#pragma unroll 1
+        for (int b = 0; b < 8; ++b) {
+            f32x16 acc2 = {};
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks)
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w2[(b * 16 + ks) * 64 + lane]),
+                                                             a1[ks], acc2, 0, 0, 0);
+            const float* bb = lbias + (b * 2 + h) * 16;
+            bf16x8 lo, hi;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const __bf16 q = (__bf16)gelu_f(acc2[r] + bb[r]);
+                if (r < 8) lo[r] = q;
+                else hi[r - 8] = q;
+            }
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w3[(2 * b) * 64 + lane]), lo, acc3,
+                                                         0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w3[(2 * b + 1) * 64 + lane]), hi,
+                                                         acc3, 0, 0, 0);
+        }
+        // outputs: register r holds output o = 8 (r / 4) + 4 h + (r % 4) of symbol n
+        int txl = 0;
+        if (a.tx && active) {
+            uint32_t row = a.tx[n];
+            if (row >= (uint32_t)a.M) {
+                if (a.bad_tx) atomicOr(a.bad_tx, 1u);
+                row = 0;
+            }
+            txl = a.row2label[row];
+        }
+        const float* b3 = lbias + 8 * 2 * 16 + h * 16;
+        float g = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = 8 * (r >> 2) + 4 * h + (r & 3);
+            if (o < a.m) {
+                const float lam = acc3[r] + b3[r];
+                if (a.llr && active) a.llr[(size_t)n * a.m + o] = lam;
+                g += gmi_bit_term(lam * 1.4426950408889634f, (txl >> (a.m - 1 - o)) & 1);
+            }
+        }
+        if (a.acc) gsum += wave_sum(active ? (double)g : 0.0);
+    }
+    if (a.acc && lane == 0) acc_add(a.acc, 0, slot, 0, gsum);
+}
+
+}  // namespace
+
+size_t mlp_frag_count() { return kFrags; }
+
+hipError_t launch_mlp_pack(const __bf16* W1t, const __bf16* W2t, const __bf16* W3t, const float* b1, uint4* frag,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(pack_kernel, dim3((kFrags + 255) / 256), dim3(256), 0, st, W1t, W2t, W3t, b1, frag);
+    return hipGetLastError();
+}
+
+hipError_t prepare_mlp_infer() {
+    return hipFuncSetAttribute((const void*)mlp_infer_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+}
+
+hipError_t launch_mlp_infer(const MlpInferArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(kThreads), kLdsBytes, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace dm

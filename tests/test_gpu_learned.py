@@ -1,0 +1,312 @@
+"""Learned demapper on the GPU: gradients, Adam, inference, audit / fallback, training, checkpoints.
+
+* Per-symbol-variance exact LLRs (the training targets) against the FP64 oracle.
+* Gradients of one batch against the FP64 oracle network with the kernels' BF16 storage points
+  emulated (tight bound) and against the plain FP64 network (cosine >= 0.999, max error
+  <= 2e-2 RMS per tensor).
+* Adam's first step against its closed form -lr g / (|g| + eps), g the GPU gradient.
+* Fused inference (LLRs and GMI) against the oracle network's forward pass.
+* Every fallback reason, and that fallback results are the exact path's.
+* Training a 2D 16-point constellation brings the learned GMI close to the exact GMI, and two
+  trainings from the same start are bit-identical.
+* A checkpoint round trip restores weights, state and outputs.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2108_07004_amd as dm
+import workloads as W
+from gpu_helpers import LLR_TOL_FP32, rel_err
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _gauss():
+    return W.gaussian_constellation(2048, 8, 2)
+
+
+def _weights(D, m, bias_sd=0.1, extra=0):
+    w = W.mlp_init_weights(D, 256, m)
+    g = W.rng(4, "misc", 100 + extra)
+    for k in ("b1", "b2", "b3"):
+        w[k] = g.normal(0.0, bias_sd, w[k].shape).astype(np.float32)
+    return w
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _snr_of(sigma2):
+    return -10.0 * np.log10(2.0 * np.asarray(sigma2, dtype=np.float64))
+
+
+def _w64(w):
+    return {k: np.asarray(v, dtype=np.float64) for k, v in w.items()}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", LLR_TOL_FP32), ("bf16x3", 5e-3)])
+def test_llr_per_symbol_variance_matches_oracle(prec, tol):
+    c = _gauss()
+    const = dm.Constellation(c.points, c.labels)
+    N = 3001
+    g = W.rng(4, "misc", 1)
+    levels = np.array([0.0, 4.0, 9.5, 15.0])
+    pick = g.integers(0, 4, N)
+    s2 = W.sigma2_from_snr_db(levels)[pick].astype(np.float32)
+    tx = W.tx_indices(2048, N, 4, 1)
+    z = W.unit_noise(N, 8, 4, 1)
+    y = (c.points.astype(np.float64)[tx] + np.sqrt(s2.astype(np.float64))[:, None] * z).astype(np.float32)
+    got = dm.demap_llr_var(const, _dev(s2), _dev(y), prec=prec).cpu().numpy()
+    for k in range(4):
+        idx = np.nonzero(pick == k)[0]
+        ref = oracle.demap(c.points, c.labels, float(s2[idx[0]]), y[idx], tx[idx])
+        e = rel_err(got[idx], ref["llr"])
+        assert e <= tol, (prec, levels[k], e)
+
+
+def test_llr_per_symbol_variance_rejects_fp16():
+    c = _gauss()
+    const = dm.Constellation(c.points, c.labels)
+    with pytest.raises(dm.DemapError):
+        dm.demap_llr_var(const, _dev(np.ones(4, np.float32)), _dev(np.zeros((4, 8), np.float32)), prec="fp16x3")
+
+
+def _grad_case(B=1024):
+    c = _gauss()
+    w = _weights(8, 11)
+    y, s2, tx, _ = W.mlp_samples(c, B, 0.0, 15.0, 4, "mlp_eval", 1)
+    T = W.rng(4, "misc", 2).normal(0.0, 4.0, (B, 11)).astype(np.float32)
+    X = mlp.features(y, _snr_of(s2))
+    return c, w, y, s2, T, X
+
+
+def test_gradients_match_oracle():
+    c, w, y, s2, T, X = _grad_case()
+    const = dm.Constellation(c.points, c.labels)
+    net = dm.MLP(const, w)
+    grads, loss = net.gradients(_dev(y), _dev(s2), _dev(T))
+    # the oracle network with the kernels' BF16 storage points
+    out, cache = mlp.forward_stored(_w64(w), X)
+    ref = mlp.backward_stored(_w64(w), cache, out, T.astype(np.float64))
+    ref_loss = mlp.loss(out, T.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (loss, ref_loss)
+    # the plain FP64 network (no storage rounding)
+    out64, cache64 = mlp.forward(_w64(w), X)
+    ref64 = mlp.backward(_w64(w), cache64, out64, T.astype(np.float64))
+    report = {}
+    for k in ref:
+        gk = grads[k].astype(np.float64).ravel()
+        for name, r, cos_min, max_rel in (("stored", ref[k], 0.99999, 2e-3), ("fp64", ref64[k], 0.999, 2e-2)):
+            r = r.ravel()
+            rms = float(np.sqrt(np.mean(r * r)))
+            cos = float(gk @ r / (np.linalg.norm(gk) * np.linalg.norm(r)))
+            mx = float(np.max(np.abs(gk - r))) / rms
+            report[(k, name)] = (cos, mx)
+            assert cos >= cos_min and mx <= max_rel, (k, name, cos, mx)
+    print("gradient agreement (cosine, max err / RMS):", report)
+
+
+def test_adam_first_step_closed_form():
+    c, w, y, s2, _, _ = _grad_case()
+    const = dm.Constellation(c.points, c.labels)
+    net = dm.MLP(const, w)
+    y_t, s2_t = _dev(y), _dev(s2)
+    target = dm.demap_llr_var(const, s2_t, y_t, prec="fp32")
+    g, _ = net.gradients(y_t, s2_t, target)
+    lr = 1e-3
+    net.train(const, y_t, s2_t, batch=1024, epochs=1, lr=lr, lr_final=lr, target_prec="fp32", snr_range=(0.0, 15.0))
+    w1 = net.get_weights()
+    assert net.info()["steps"] == 1
+    for k in w:
+        gk = g[k].astype(np.float64)
+        want = w[k].astype(np.float64) - lr * gk / (np.abs(gk) + 1e-8)
+        err = np.abs(w1[k].astype(np.float64) - want)
+        bound = 1e-6 * lr + 2.0 ** -23 * np.abs(want)
+        assert np.all(err <= bound), (k, float(np.max(err / bound)))
+
+
+def _infer_ref(w, y, sigma2):
+    """Oracle forward with the inference kernel's storage: BF16 weights, inputs and activations,
+    the first-layer bias as a BF16 hi + lo pair."""
+    b1 = np.asarray(w["b1"], dtype=np.float32)
+    hi = mlp.bf16_round(b1)
+    lo = mlp.bf16_round((b1 - hi.astype(np.float32)).astype(np.float32))
+    X = mlp.features(y, _snr_of(sigma2))
+    out, _ = mlp.forward_stored(_w64(w), X, b1=hi + lo)
+    return out
+
+
+def test_inference_matches_oracle_forward():
+    import torch
+    c = _gauss()
+    const = dm.Constellation(c.points, c.labels)
+    w = _weights(8, 11, bias_sd=0.3, extra=1)
+    net = dm.MLP(const, w)
+    N = 3001  # 93 full tiles of 32 symbols and a ragged tail
+    snr = np.array([0.0, 7.0, 15.0])
+    s2 = W.sigma2_from_snr_db(snr)
+    tx = W.tx_indices(2048, N, 4, 3)
+    z = W.unit_noise(N, 8, 4, 3)
+    ys = [W.awgn(c.points, tx, z, v) for v in s2]
+    llrs = [torch.full((N, 11), float("nan"), device=DEV) for _ in s2]
+    gmi, loss, fb = dm.demap_learned(net, const, s2, [_dev(v) for v in ys], _dev(tx.view(np.int16)), llrs,
+                                     max_gmi_loss=-1.0)
+    assert np.all(fb == 0) and np.all(np.isnan(loss))
+    lab = c.labels[tx]
+    for i, v in enumerate(s2):
+        ref = _infer_ref(w, ys[i], v)
+        got = llrs[i].cpu().numpy().astype(np.float64)
+        rms = float(np.sqrt(np.mean(ref * ref)))
+        mx = float(np.max(np.abs(got - ref))) / rms
+        print(f"inference snr={snr[i]}: max err / RMS = {mx:.2e}")
+        assert mx <= 5e-3, (snr[i], mx)
+        g_ref = oracle.gmi_from_llr(11, ref, lab)
+        assert abs(gmi[i] - g_ref) <= 1e-3, (snr[i], gmi[i], g_ref)
+
+
+def test_inference_without_tx_and_empty_block():
+    import torch
+    c = _gauss()
+    const = dm.Constellation(c.points, c.labels)
+    net = dm.MLP(const, _weights(8, 11))
+    N = 77
+    y = W.awgn(c.points, W.tx_indices(2048, N, 4, 4), W.unit_noise(N, 8, 4, 4), 0.05)
+    llr = torch.empty((N, 11), device=DEV)
+    gmi, loss, fb = dm.demap_learned(net, const, [0.05], [_dev(y)], None, [llr])
+    assert fb[0] == 0 and np.isnan(gmi[0])
+    ref = _infer_ref(net.get_weights(), y, 0.05)
+    assert np.max(np.abs(llr.cpu().numpy() - ref)) <= 5e-3 * np.sqrt(np.mean(ref * ref))
+    e = torch.empty((0, 8), device=DEV)
+    gmi, loss, fb = dm.demap_learned(net, const, [0.05], [e], torch.empty(0, dtype=torch.int16, device=DEV), None)
+    assert np.isnan(gmi[0]) and fb[0] == 0
+
+
+def test_fallback_reasons_return_exact_results():
+    import torch
+    c = _gauss()
+    const = dm.Constellation(c.points, c.labels)
+    other = W.gaussian_constellation(2048, 8, 2, 7)
+    const_other = dm.Constellation(other.points, other.labels)
+    net = dm.MLP(const, _weights(8, 11))  # untrained: far from the exact LLRs
+    N = 20000
+    tx = W.tx_indices(2048, N, 4, 5)
+    z = W.unit_noise(N, 8, 4, 5)
+    snr = np.array([6.0, 12.0])
+    s2 = W.sigma2_from_snr_db(snr)
+    tx_t = _dev(tx.view(np.int16))
+    for cc, hc, want in ((c, const, 1), (other, const_other, 3)):
+        ys = [_dev(W.awgn(cc.points, tx, z, v)) for v in s2]
+        llrs = [torch.empty((N, 11), device=DEV) for _ in s2]
+        gmi, loss, fb = dm.demap_learned(net, hc, s2, ys, tx_t, llrs, max_gmi_loss=0.01, exact_prec="fp32")
+        assert np.all(fb == want), (want, fb)
+        ref = [torch.empty((N, 11), device=DEV) for _ in s2]
+        g_ex, _ = dm.gmi_estimate(hc, s2, ys, tx_t, ref, prec="fp32")
+        assert np.array_equal(gmi, g_ex), (gmi, g_ex)  # the same exact launch over both points
+        for a, b in zip(llrs, ref):
+            assert torch.equal(a, b)
+        if want == 1:
+            assert np.all(loss > 0.01)
+        else:
+            assert np.all(np.isnan(loss))
+
+
+def test_fallback_outside_trained_snr_range():
+    c = _gauss()
+    const = dm.Constellation(c.points, c.labels)
+    net = dm.MLP(const, _weights(8, 11))
+    y, s2, _, _ = W.mlp_samples(c, 2048, 5.0, 10.0, 4, "mlp_train", 9)
+    net.train(const, _dev(y), _dev(s2), batch=1024, epochs=1, lr=1e-4, lr_final=1e-4, snr_range=(5.0, 10.0))
+    info = net.info()
+    assert info["steps"] == 2 and info["snr_lo_db"] == 5.0 and info["snr_hi_db"] == 10.0
+    N = 4096
+    tx = W.tx_indices(2048, N, 4, 6)
+    z = W.unit_noise(N, 8, 4, 6)
+    snr = np.array([2.0, 7.0, 13.0])
+    s2e = W.sigma2_from_snr_db(snr)
+    ys = [_dev(W.awgn(c.points, tx, z, v)) for v in s2e]
+    gmi, loss, fb = dm.demap_learned(net, const, s2e, ys, _dev(tx.view(np.int16)), None, max_gmi_loss=-1.0)
+    assert fb.tolist() == [2, 0, 2]
+    g_ex, _ = dm.gmi_estimate(const, s2e, ys, _dev(tx.view(np.int16)))
+    # the same exact values up to the grid's fixed-point partial-sum rounding (2^-28 per wave)
+    assert abs(gmi[0] - g_ex[0]) <= 1e-9 and abs(gmi[2] - g_ex[2]) <= 1e-9
+
+
+def _qam16():
+    return W.product_pam(4, 2, "16qam")
+
+
+def _train_qam(seed_extra=0):
+    c = _qam16()
+    const = dm.Constellation(c.points, c.labels)
+    net = dm.MLP(const, W.mlp_init_weights(2, 256, 4))
+    y, s2, _, _ = W.mlp_samples(c, 1 << 18, 0.0, 15.0, 4, "mlp_train", 20 + seed_extra)
+    loss = net.train(const, _dev(y), _dev(s2), batch=1024, epochs=2, lr=3e-3, lr_final=3e-5)
+    return c, const, net, loss
+
+
+def test_training_approaches_exact_gmi():
+    c, const, net, final_loss = _train_qam()
+    N = 1 << 16
+    tx = W.tx_indices(16, N, 4, 30)
+    z = W.unit_noise(N, 2, 4, 30)
+    snr = np.array([2.0, 8.0, 14.0])
+    s2 = W.sigma2_from_snr_db(snr)
+    ys = [_dev(W.awgn(c.points, tx, z, v)) for v in s2]
+    tx_t = _dev(tx.view(np.int16))
+    g_l, loss_est, fb = dm.demap_learned(net, const, s2, ys, tx_t, None, max_gmi_loss=-1.0)
+    g_ex, _ = dm.gmi_estimate(const, s2, ys, tx_t)
+    print("16-point training: final loss", final_loss, "exact", g_ex, "learned", g_l)
+    assert np.all(fb == 0)
+    assert np.all(g_ex - g_l <= 0.05), (g_ex, g_l)
+    # the initial network is far from it
+    net0 = dm.MLP(const, W.mlp_init_weights(2, 256, 4))
+    g0, _, _ = dm.demap_learned(net0, const, s2, ys, tx_t, None, max_gmi_loss=-1.0)
+    assert np.all(g_ex - g0 > 0.2), g0
+    # with the audit on, the trained network passes where its loss is small
+    g_a, loss_a, fb_a = dm.demap_learned(net, const, s2, ys, tx_t, None, max_gmi_loss=0.05)
+    assert np.all(fb_a == 0) and np.all(np.abs(loss_a) < 0.05)
+    assert np.max(np.abs(g_a - g_l)) <= 1e-9  # prefix + rest launches vs one launch
+
+
+def test_training_is_deterministic():
+    _, _, net_a, la = _train_qam()
+    _, _, net_b, lb = _train_qam()
+    wa, wb = net_a.get_weights(), net_b.get_weights()
+    assert la == lb
+    for k in wa:
+        assert np.array_equal(wa[k], wb[k]), k
+
+
+def test_checkpoint_round_trip(tmp_path):
+    import torch
+    c, const, net, _ = _train_qam()
+    p = tmp_path / "net.bin"
+    net.save(str(p))
+    net2 = dm.MLP.load(const, str(p))
+    assert net2.info() == net.info()
+    w1, w2 = net.get_weights(), net2.get_weights()
+    for k in w1:
+        assert np.array_equal(w1[k], w2[k])
+    N = 999
+    y = _dev(W.awgn(c.points, W.tx_indices(16, N, 4, 31), W.unit_noise(N, 2, 4, 31), 0.03))
+    l1, l2 = torch.empty((N, 4), device=DEV), torch.empty((N, 4), device=DEV)
+    dm.demap_learned(net, const, [0.03], [y], None, [l1])
+    dm.demap_learned(net2, const, [0.03], [y], None, [l2])
+    assert torch.equal(l1, l2)
+    # training continues from the restored Adam state exactly as from the original
+    ys, s2s, _, _ = W.mlp_samples(c, 2048, 0.0, 15.0, 4, "mlp_train", 40)
+    net.train(const, _dev(ys), _dev(s2s), batch=1024, lr=1e-4, lr_final=1e-4)
+    net2.train(const, _dev(ys), _dev(s2s), batch=1024, lr=1e-4, lr_final=1e-4)
+    w1, w2 = net.get_weights(), net2.get_weights()
+    for k in w1:
+        assert np.array_equal(w1[k], w2[k])
+    with pytest.raises(dm.DemapError):
+        dm.MLP.load(dm.Constellation(_gauss().points, _gauss().labels), str(p))

@@ -101,3 +101,32 @@ def test_seeded_initial_weights_shapes():
     assert np.all(w["b1"] == 0) and abs(float(np.max(np.abs(w["W2"]))) - 0.5 * math.sqrt(6 / 256)) < 1e-3
     w2 = W.mlp_init_weights(8, 256, 11)
     assert all(np.array_equal(w[k], w2[k]) for k in w)
+
+
+def test_bf16_rounding_known_values():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: ties go to the even mantissa (1.0)
+    vals = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20, -2.5, 3.0e38, 0.0])
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, -2.5, 2.9993e38, 0.0])
+    got = mlp.bf16_round(vals)
+    assert np.all(np.abs(got[:5] - want[:5]) == 0.0)
+    assert abs(got[5] / 3.0e38 - 1.0) < 2.0 ** -8 and got[6] == 0.0
+    # every output is representable: 8 significant bits
+    x = np.random.default_rng(0).normal(0, 10, 1000)
+    r = mlp.bf16_round(x)
+    m, e = np.frexp(r)
+    assert np.all(m * 256 == np.round(m * 256))
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_stored_rounding_hooks_reduce_to_the_pinned_network():
+    w, X, T = _tiny()
+    out, cache = mlp.forward(w, X)
+    out2, cache2 = mlp.forward_stored(w, X, rnd=mlp.identity)
+    assert np.array_equal(out, out2)
+    g = mlp.backward(w, cache, out, T)
+    g2 = mlp.backward_stored(w, cache2, out2, T, rnd=mlp.identity)
+    for k in g:
+        assert np.array_equal(g[k], g2[k]), k
+    # with BF16 storage the result moves by about the BF16 resolution, not more
+    out3, _ = mlp.forward_stored(w, X)
+    assert 0 < np.max(np.abs(out3 - out)) < 0.05 * np.max(np.abs(out))

@@ -284,3 +284,42 @@ def batched_instances(count: int = 64, n_lo: int = 14, n_hi: int = 22) -> list:
             c = gaussian_constellation(M, D, 3, i)
         out.append(Instance(i, c, N, snr))
     return out
+
+
+def mlp_samples(const: Constellation, N: int, snr_lo: float = 0.0, snr_hi: float = 15.0, config: int = 4,
+                purpose: str = "mlp_train", *extra: int):
+    """Training / evaluation samples of the learned demapper: uniform transmitted rows, an SNR per
+    sample drawn uniformly (continuous, dB) from [snr_lo, snr_hi], y = fl32(x + sigma z).
+
+    Returns (y float32 (N, D), sigma2 float32 (N,), tx uint16 (N,), snr_db float64 (N,)).
+    """
+    g = rng(config, purpose, *extra)
+    M, D = const.points.shape
+    tx = g.integers(0, M, size=N, dtype=np.int64)
+    snr = g.uniform(snr_lo, snr_hi, size=N)
+    z = g.standard_normal((N, D))
+    s2 = sigma2_from_snr_db(snr)
+    y = (const.points.astype(np.float64)[tx] + np.sqrt(s2)[:, None] * z).astype(np.float32)
+    return y, s2.astype(np.float32), tx.astype(np.uint16), snr
+
+
+def mlp_samples_torch(points, N: int, snr_lo: float, snr_hi: float, device, config: int = 4, *extra: int):
+    """Device-side twin of ``mlp_samples`` for large N (torch's seeded generator on the GPU; the
+    stream differs from NumPy's).  Returns (y float32 (N, D), sigma2 float32 (N,)) tensors."""
+    import torch
+    seed = int(np.random.SeedSequence(BASE_SEED, spawn_key=(int(config), _PURPOSES["mlp_train"]) +
+                                      tuple(int(e) for e in extra)).generate_state(1, np.uint64)[0] >> 1)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    pts = torch.as_tensor(np.asarray(points), dtype=torch.float32).to(device)
+    M, D = pts.shape
+    tx = torch.randint(0, M, (N,), generator=g, device=device)
+    snr = torch.rand(N, generator=g, device=device, dtype=torch.float64) * (snr_hi - snr_lo) + snr_lo
+    s2 = 1.0 / (2.0 * torch.pow(10.0, snr / 10.0))
+    y = torch.empty((N, D), dtype=torch.float32, device=device)
+    step = 1 << 22
+    for a in range(0, N, step):
+        b = min(N, a + step)
+        z = torch.randn((b - a, D), generator=g, device=device, dtype=torch.float64)
+        y[a:b] = (pts[tx[a:b]].to(torch.float64) + torch.sqrt(s2[a:b])[:, None] * z).to(torch.float32)
+    return y, s2.to(torch.float32)
