@@ -156,6 +156,37 @@ def bench_learned(const, w, ys, tx_t, llrs, exact_gmi, exact_sym_per_s, exact_pr
     }
 
 
+FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (an FMA counts 2)
+
+
+def bench_hard(const, w, ys, tx_t, steps):
+    """Minimum-distance decisions of the headline block (labels written, symbol / bit errors counted)."""
+    import torch
+
+    import paper_2108_07004_amd as dm
+
+    dev = torch.device("cuda:0")
+    outs = [torch.empty(w.N, dtype=torch.int16, device=dev) for _ in ys]
+    se = be = None
+    dm.hard_decision(const, ys, tx_t, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        se, be = dm.hard_decision(const, ys, tx_t, outs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    n_sym = w.N * len(ys)
+    pairs = float(n_sym) * w.const.M
+    flops = pairs * 3 * w.const.D  # per (symbol, point): D subtractions + D fused multiply-adds
+    ber = be / (w.N * w.const.m)
+    return {"workload": f"{w.name}: N={w.N} x {len(ys)} blocks, min-distance labels + symbol/bit error counts",
+            "symbols_per_s": n_sym / dt, "ms_per_step": dt * 1e3,
+            "roofline": {"bound": "alu", "achieved": flops / dt / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": flops / dt / FP32_VECTOR_PEAK, "traffic": None},
+            "ser": [float(v) / w.N for v in se], "ber": [float(v) for v in ber],
+            "q_db": [None if not (0 < b < 0.5) else round(dm.q_factor_db(float(b)), 3) for b in ber]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +198,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip training + timing the learned demapper")
+    ap.add_argument("--no-hard", action="store_true", help="skip the hard-decision measurement")
     ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
     ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -263,6 +295,10 @@ def main():
         out["batched"] = bench_batched(args.prec if args.prec != "fp32" else "fp16x3", max(3, args.steps), 2)
         log(f"batched: {out['batched']['ms_per_launch']:.3f} ms/launch, "
             f"{out['batched']['symbols_per_s'] / 1e9:.3f} Gsym/s")
+    if not args.no_hard:
+        log("hard decisions: minimum-distance labels + error counts")
+        out["hard_decision"] = bench_hard(const, w, ys, tx_t, max(2, min(args.steps, 5)))
+        log(f"hard decisions: {out['hard_decision']['symbols_per_s'] / 1e9:.3f} Gsym/s")
     if not args.no_learned and w.name == "gauss8d2048":
         log("learned: training on the GPU, then learned vs exact demapping")
         out["learned"] = bench_learned(const, w, ys, tx_t, llrs, gmi, value, args.prec, args.learned_train,

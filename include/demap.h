@@ -261,6 +261,54 @@ int dm_mlp_save(const dm_mlp* net, const char* path);
  * so a different table makes dm_demap_learned fall back). */
 int dm_mlp_load(const dm_constellation* c, const char* path, dm_mlp** out);
 
+/*
+ * Hard decisions: the minimum-Euclidean-distance point of each received symbol (the
+ * paper's receiver decides symbols by minimum distance over the uploaded table, Sec. 2) and,
+ * with tx, the symbol- and bit-error counts behind its BER / Q-factor figures (Sec. 4).
+ *   y           HOST array of n_blk DEVICE pointers, each N x D FP32.
+ *   tx          DEVICE, N uint16 transmitted ROW indices; required when counting, else may be NULL.
+ *   labels_out  HOST array of n_blk DEVICE pointers (N uint16 decided LABELS each) or NULL.
+ *   sym_err, bit_err  HOST int64 n_blk outputs, or NULL (no counting, no synchronisation).
+ * Distances are FP32: t_d = y_d - x_d, acc = fma(t_d, t_d, acc) for d = 0..D-1 from acc = 0;
+ * ties go to the lowest label.  Bit errors are the popcount of (decided label XOR sent label).
+ * Synchronises `stream` when counting.  Errors: DM_EINVAL, DM_EHIP, DM_ENOMEM.
+ */
+int dm_hard_decision(const dm_constellation* c, int n_blk, const float* const* y, const uint16_t* tx, int64_t N,
+                     uint16_t* const* labels_out, int64_t* sym_err, int64_t* bit_err, void* stream);
+
+/* Q-factor in dB from a bit-error ratio, 20 log10(sqrt(2) erfcinv(2 BER)) (the usual Gaussian
+ * reading; the paper quotes Q-factors without a formula).  NaN unless 0 < ber < 0.5. */
+double dm_q_factor_db(double ber);
+
+/*
+ * Geometric-shaping search by AWGN GMI (the paper's iterative design of its GS constellations,
+ * Sec. 5): from the given constellation, each iteration proposes `candidates` modifications of
+ * the current one -- with probability swap_prob the labels of two random points are swapped,
+ * otherwise one random point moves by perturb_sd * N(0, I) and the constellation is rescaled to
+ * unit energy per two dimensions -- evaluates all of them in one batched FP32 GMI launch on the
+ * common block (tx, z) at snr_db, and keeps the best one if its GMI exceeds the current GMI.
+ * Random draws come from SplitMix64 seeded with `seed`.
+ *   points, labels  HOST initial constellation (M x D, any row order; rescaled to unit energy).
+ *   tx              DEVICE, N uint16 transmitted LABELS.   z  DEVICE, N x D FP32 unit noise.
+ *   out_points      HOST M x D result in label order (row l carries label l).
+ *   gmi_trace       HOST iters + 1 values: the current GMI after each iteration (index 0: start).
+ *   accepted        HOST, number of accepted iterations, or NULL.
+ * Limits: M a power of two <= 4096, D <= 8, 1 <= candidates <= 64.  Device memory: candidates
+ * x N x D FP32 received blocks.  Synchronous.  Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_ENOMEM, DM_EHIP.
+ */
+typedef struct dm_gs_config {
+    double snr_db;       /* SNR (unit energy per 2D) of the AWGN GMI */
+    int32_t iters;       /* iterations, >= 0 */
+    int32_t candidates;  /* modifications evaluated per iteration, 1..64 */
+    double perturb_sd;   /* standard deviation of a point move (per dimension) */
+    double swap_prob;    /* probability that a modification is a label swap */
+    uint64_t seed;
+} dm_gs_config;
+
+int dm_gs_optimize(const float* points, const uint16_t* labels, int32_t M, int32_t D, const dm_gs_config* cfg,
+                   const uint16_t* tx, const float* z, int64_t N, float* out_points, double* gmi_trace,
+                   int32_t* accepted, void* stream);
+
 /* Number of (symbol, bit) pairs that the last call on this thread sent through the
  * far-subset underflow fix-up, per SNR point (HOST array of n_snr, may be NULL).
  * Returns the total, or a negative DM_E* if no call has run on this thread. */

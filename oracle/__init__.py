@@ -51,6 +51,8 @@ def _load():
         lib.oracle_gmi_from_llr.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P]
         lib.oracle_gmi_from_llr.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_hard_demap.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int64, P, P, P]
+        lib.oracle_hard_demap.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -101,3 +103,24 @@ def gmi_from_llr(m, llr, tx_label):
     if rc != 0:
         raise ValueError("oracle_gmi_from_llr rejected its arguments")
     return float(out[0])
+
+
+def hard_demap(points, labels, y, tx=None):
+    """Minimum-distance decisions (FP32 fused distance, ties to the lowest label) and, with tx,
+    the symbol and bit error counts.  Returns dict(labels=(N,) uint16, sym_err=int, bit_err=int)."""
+    lib = _load()
+    points = np.ascontiguousarray(points, dtype=np.float32)
+    labels = np.ascontiguousarray(labels, dtype=np.uint16)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    M, D = points.shape
+    N = int(y.shape[0])
+    if y.ndim != 2 or y.shape[1] != D:
+        raise ValueError("shape mismatch")
+    out = np.empty(N, dtype=np.uint16)
+    txa = None if tx is None else np.ascontiguousarray(tx, dtype=np.uint16)
+    se = np.zeros(1, dtype=np.int64)
+    be = np.zeros(1, dtype=np.int64)
+    rc = lib.oracle_hard_demap(M, D, _ptr(points), _ptr(labels), _ptr(y), _ptr(txa), N, _ptr(out), _ptr(se), _ptr(be))
+    if rc != 0:
+        raise ValueError(f"oracle_hard_demap rejected its arguments (rc={rc})")
+    return {"labels": out, "sym_err": int(se[0]), "bit_err": int(be[0])}

@@ -180,3 +180,48 @@ int oracle_max_threads(void) {
     return 1;
 #endif
 }
+
+/*
+ * Hard decisions by minimum Euclidean distance (the receiver's decision rule, Sec. 2) and
+ * their symbol / bit errors against the transmitted labels (the BER behind the paper's
+ * Q-factors, Sec. 4).  The decision is an integer taken from floating-point distances, so it
+ * is taken in the single-precision formula the library documents: t_d = y_d - x_d,
+ * acc = fmaf(t_d, t_d, acc) over d = 0..D-1 starting from 0.  Every row is scanned; the
+ * smallest distance wins and equal distances go to the smallest label.  A NaN distance never
+ * wins.  out_label (N) may be NULL; tx (N rows) may be NULL, then the counts are not formed.
+ */
+int oracle_hard_demap(int M, int D, const float* points, const uint16_t* labels, const float* y,
+                      const uint16_t* tx, int64_t N, uint16_t* out_label, int64_t* sym_err, int64_t* bit_err) {
+    if (M < 1 || D < 1 || N < 0 || !points || !labels || (N > 0 && !y)) return ORACLE_EINVAL;
+    int64_t se = 0, be = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        float best = INFINITY;
+        int best_label = -1;
+        for (int j = 0; j < M; ++j) {
+            float acc = 0.0f;
+            for (int d = 0; d < D; ++d) {
+                const float t = y[n * D + d] - points[(size_t)j * D + d];
+                acc = fmaf(t, t, acc);
+            }
+            if (acc < best || (acc == best && labels[j] < best_label)) {
+                best = acc;
+                best_label = labels[j];
+            }
+        }
+        if (best_label < 0) { /* every distance NaN: the lowest label */
+            best_label = M;
+            for (int j = 0; j < M; ++j)
+                if (labels[j] < best_label) best_label = labels[j];
+        }
+        if (out_label) out_label[n] = (uint16_t)best_label;
+        if (tx) {
+            if (tx[n] >= M) return ORACLE_EINVAL;
+            const unsigned diff = (unsigned)best_label ^ labels[tx[n]];
+            se += diff != 0;
+            for (unsigned v = diff; v; v >>= 1) be += v & 1u;
+        }
+    }
+    if (sym_err) *sym_err = se;
+    if (bit_err) *bit_err = be;
+    return ORACLE_OK;
+}

@@ -17,7 +17,7 @@ from typing import Sequence
 import numpy as np
 
 __all__ = ["Constellation", "DemapError", "MLP", "PREC", "Plan", "demap_batched", "demap_learned", "demap_llr",
-           "demap_llr_var", "gmi_estimate", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
+           "demap_llr_var", "gmi_estimate", "gs_optimize", "hard_decision", "q_factor_db", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
            "probe_valu_rates", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
@@ -98,6 +98,12 @@ def load_library():
     lib.dm_mlp_save.restype = I
     lib.dm_mlp_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P)]
     lib.dm_mlp_load.restype = I
+    lib.dm_hard_decision.argtypes = [P, I, P, P, I64, P, P, P, P]
+    lib.dm_hard_decision.restype = I
+    lib.dm_q_factor_db.argtypes = [D]
+    lib.dm_q_factor_db.restype = D
+    lib.dm_gs_optimize.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, I64, P, P, P, P]
+    lib.dm_gs_optimize.restype = I
     lib.dm_last_error.restype = ctypes.c_char_p
     lib.dm_version.restype = ctypes.c_char_p
     _lib = lib
@@ -486,3 +492,61 @@ def demap_learned(net: MLP, const: Constellation, sigma2: Sequence[float], ys, t
         gmi.ctypes.data_as(ctypes.c_void_p), loss.ctypes.data_as(ctypes.c_void_p), fb.ctypes.data_as(ctypes.c_void_p),
         _stream_handle(stream)))
     return gmi, loss, fb
+
+
+def hard_decision(const: Constellation, ys, tx=None, labels=None, count: bool = True, stream=None):
+    """Minimum-distance decisions of n_blk received blocks (dm_hard_decision).
+
+    ys: list of (N, D) FP32 tensors; tx: (N,) int16/uint16 rows (needed for counting);
+    labels: None or a list of (N,) int16/uint16 tensors receiving the decided labels.
+    Returns (symbol_errors, bit_errors) int64 NumPy arrays, or (None, None) without counting.
+    """
+    nb = len(ys)
+    N = int(ys[0].shape[0])
+    yptr = (ctypes.c_void_p * nb)(*[_dev_tensor(t, ("float32",), (N, const.D), "y[s]").value for t in ys])
+    txp = None if tx is None else _dev_tensor(tx, ("int16", "uint16"), (N,), "tx")
+    lptr = None
+    if labels is not None:
+        lptr = (ctypes.c_void_p * nb)(*[_dev_tensor(t, ("int16", "uint16"), (N,), "labels[s]").value for t in labels])
+    se = np.zeros(nb, dtype=np.int64) if count else None
+    be = np.zeros(nb, dtype=np.int64) if count else None
+    _check(load_library().dm_hard_decision(
+        const.handle, nb, ctypes.cast(yptr, ctypes.c_void_p), txp, N,
+        None if lptr is None else ctypes.cast(lptr, ctypes.c_void_p),
+        None if se is None else se.ctypes.data_as(ctypes.c_void_p),
+        None if be is None else be.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)))
+    return se, be
+
+
+def q_factor_db(ber: float) -> float:
+    """20 log10(sqrt(2) erfcinv(2 BER)) (dm_q_factor_db); NaN outside 0 < BER < 0.5."""
+    return float(load_library().dm_q_factor_db(float(ber)))
+
+
+class _GsConfig(ctypes.Structure):
+    _fields_ = [("snr_db", ctypes.c_double), ("iters", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("perturb_sd", ctypes.c_double), ("swap_prob", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+def gs_optimize(points, labels, snr_db: float, tx, z, iters: int = 200, candidates: int = 32,
+                perturb_sd: float = 0.05, swap_prob: float = 0.3, seed: int = 1, stream=None):
+    """GMI-driven geometric-shaping search (dm_gs_optimize).
+
+    tx: (N,) int16/uint16 tensor of transmitted LABELS; z: (N, D) FP32 unit-noise tensor.
+    Returns (points (M, D) float32 in label order, labels = arange(M), gmi_trace (iters+1,), accepted).
+    """
+    pts = np.ascontiguousarray(points, dtype=np.float32)
+    lab = np.ascontiguousarray(labels, dtype=np.uint16)
+    M, D = pts.shape
+    N = int(tx.shape[0])
+    txp = _dev_tensor(tx, ("int16", "uint16"), (N,), "tx")
+    zp = _dev_tensor(z, ("float32",), (N, D), "z")
+    out = np.empty((M, D), dtype=np.float32)
+    trace = np.empty(iters + 1, dtype=np.float64)
+    acc = ctypes.c_int32()
+    cfg = _GsConfig(float(snr_db), int(iters), int(candidates), float(perturb_sd), float(swap_prob), int(seed))
+    _check(load_library().dm_gs_optimize(pts.ctypes.data_as(ctypes.c_void_p), lab.ctypes.data_as(ctypes.c_void_p),
+                                         M, D, ctypes.byref(cfg), txp, zp, N, out.ctypes.data_as(ctypes.c_void_p),
+                                         trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(acc),
+                                         _stream_handle(stream)))
+    return out, np.arange(M, dtype=np.uint16), trace, int(acc.value)

@@ -60,6 +60,10 @@ int gmi_run(dm_constellation* c, int n_snr, const double* sigma2, const float* c
 int llr_var_run(dm_constellation* c, const float* sigma2_sym, const float* y, int64_t N, float* llr, int prec,
                 hipStream_t st);
 uint64_t table_hash(int M, int D, const std::vector<float>& table);
+// Replace the coordinates (host, label order, M x D) of c in place; see demap_api.hip.
+int set_label_table(dm_constellation* c, const float* table);
+// Allocate the constellation's accumulators / flags / staging (and a fix-up queue of >= want entries).
+int ensure_scratch(dm_constellation* c, uint64_t want_queue);
 
 }  // namespace dmapi
 

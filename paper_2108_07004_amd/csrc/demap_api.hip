@@ -304,6 +304,46 @@ int llr_var_run(dm_constellation* c, const float* sigma2_sym, const float* y, in
     return run_chunk(c, 1, &unit, ys, nullptr, N, ls, false, prec, st, sigma2_sym);
 }
 
+// Replace the point coordinates of a constellation, given in label order (host, M x D), keeping
+// M, D and the labelling; rewrites the device tables in place (same addresses, so plans built
+// on c see the new points).  MFMA operand tables are dropped (rebuilt on next use) unless a
+// batched copy of them exists, which cannot be rebuilt in place: that case is refused.
+int set_label_table(dm_constellation* c, const float* table) {
+    std::lock_guard<std::mutex> lock(c->mu);
+    for (int p = 0; p < 5; ++p)
+        if (c->d_frag8[p]) return fail(DM_EUNSUPPORTED, "constellation has batched MFMA tables; points are fixed");
+    float mx = 0.0f;
+    for (int l = 0; l < c->M; ++l) {
+        double n = 0.0;
+        for (int d = 0; d < c->D; ++d) {
+            const float v = table[(size_t)l * c->D + d];
+            if (!std::isfinite(v) || std::fabs(v) > 1e15f) return fail(DM_EINVAL, "point coordinate is not finite");
+            n += (double)v * v;
+        }
+        mx = std::max(mx, (float)n);
+    }
+    c->h_table.assign(table, table + (size_t)c->M * c->D);
+    c->max_norm = mx;
+    c->hash = table_hash(c->M, c->D, c->h_table);
+    std::vector<float> padded((size_t)c->M * c->DP, 0.0f);
+    for (int l = 0; l < c->M; ++l)
+        for (int d = 0; d < c->D; ++d) padded[(size_t)l * c->DP + d] = table[(size_t)l * c->D + d];
+    DM_HIP_TRY(hipMemcpy(c->d_table, padded.data(), padded.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (c->d_table8) {
+        std::vector<float> t8((size_t)c->M * 8, 0.0f);
+        for (int l = 0; l < c->M; ++l)
+            for (int d = 0; d < c->D; ++d) t8[(size_t)l * 8 + d] = table[(size_t)l * c->D + d];
+        DM_HIP_TRY(hipMemcpy(c->d_table8, t8.data(), t8.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    for (int p = 0; p < 5; ++p) {
+        if (c->d_frag[p]) (void)hipFree(c->d_frag[p]);
+        if (c->d_pv[p]) (void)hipFree(c->d_pv[p]);
+        c->d_frag[p] = nullptr;
+        c->d_pv[p] = nullptr;
+    }
+    return DM_OK;
+}
+
 // FNV-1a over M, D and the label-order table: identifies the constellation a network was trained on.
 uint64_t table_hash(int M, int D, const std::vector<float>& table) {
     uint64_t h = 1469598103934665603ull;

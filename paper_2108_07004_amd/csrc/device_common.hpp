@@ -52,6 +52,19 @@ struct SnrArg {
     int32_t pad;
 };
 
+// Hard-decision launch over up to kMaxSnrPerLaunch received blocks of one transmitted block.
+struct HardArgs {
+    const float* table;          // M x DP, label order
+    const uint16_t* row2label;   // M
+    const uint16_t* tx;          // N transmitted rows (with counts)
+    const float* y[kMaxSnrPerLaunch];
+    uint16_t* labels_out[kMaxSnrPerLaunch];  // decided labels per block, or null
+    int64_t N, tiles_per_blk;
+    int M, D, n_blk;
+    unsigned long long* counts;  // [n_blk][2]: symbol errors, bit errors; null = no counting
+    uint32_t* bad_tx;
+};
+
 // Multi-SNR launch over one constellation and one transmitted block.
 struct LaunchArgs {
     const float* table;

@@ -11,6 +11,8 @@ int padded_dim(int D);
 
 // Symbols per tile of the FP32 kernel (one lane per symbol).
 int valu_tile_symbols();
+int hard_tile_symbols();
+hipError_t launch_hard_demap(const HardArgs& a, int grid, hipStream_t st);
 
 // FP32 direct-difference demapper (one lane per symbol, persistent grid).
 hipError_t launch_demap_valu(const LaunchArgs& a, int grid, hipStream_t st);

@@ -116,6 +116,23 @@ def dp_16qam() -> Constellation:
     return product_pam(4, 4, "dp-16qam")
 
 
+def rect_qam(levels_i: int, levels_q: int, name: str = "") -> Constellation:
+    """Rectangular QAM: BRGC PAM in each of two dimensions (I bits most significant), unit
+    energy per 2D.  rect_qam(4, 2) is the rectangular 8-QAM."""
+    ai, gi = pam_brgc(levels_i)
+    aq, gq = pam_brgc(levels_q)
+    qb = int(round(math.log2(levels_q)))
+    pts, lab = [], []
+    for i in range(levels_i):
+        for q in range(levels_q):
+            pts.append((ai[i], aq[q]))
+            lab.append((int(gi[i]) << qb) | int(gq[q]))
+    p = np.asarray(pts, dtype=np.float64)
+    p *= math.sqrt(1.0 / float(np.mean(np.sum(p * p, axis=1))))
+    return Constellation(p.astype(np.float32), np.asarray(lab, dtype=np.uint16),
+                         name or f"{levels_i * levels_q}-qam-rect")
+
+
 def pam(levels: int) -> Constellation:
     """1D BRGC PAM (used by closed-form checks)."""
     return product_pam(levels, 1, f"{levels}-pam")
