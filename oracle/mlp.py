@@ -108,30 +108,33 @@ def identity(x):
     return np.asarray(x, dtype=np.float64)
 
 
-def forward_stored(w, X, rnd=bf16_round, b1=None):
-    """Forward pass where every stored operand is rounded by `rnd`: the weights, the inputs and
-    the two hidden activations after GELU (accumulation and biases in full precision).  `b1`
-    overrides the first-layer bias (e.g. its BF16 hi + lo pair).  Returns (out, cache)."""
+def forward_stored(w, X, rnd=bf16_round, b1=None, rnd_act=None):
+    """Forward pass where every stored operand is rounded: the weights and the inputs by `rnd`,
+    the two hidden activations after GELU by `rnd_act` (default: `rnd`); accumulation and biases
+    in full precision.  `b1` overrides the first-layer bias (e.g. its BF16 hi + lo pair).
+    Returns (out, cache)."""
+    ra = rnd if rnd_act is None else rnd_act
     Xr = rnd(X)
     h1 = Xr @ rnd(w["W1"]) + (w["b1"] if b1 is None else b1)
-    a1 = rnd(gelu(h1))
+    a1 = ra(gelu(h1))
     h2 = a1 @ rnd(w["W2"]) + w["b2"]
-    a2 = rnd(gelu(h2))
+    a2 = ra(gelu(h2))
     out = a2 @ rnd(w["W3"]) + w["b3"]
     return out, (Xr, h1, a1, h2, a2)
 
 
-def backward_stored(w, cache, out, llr_target, rnd=bf16_round):
-    """Gradients of `loss` with the stored back-propagated deltas rounded by `rnd` (the output
-    delta and the two hidden deltas), weights rounded as in forward_stored."""
+def backward_stored(w, cache, out, llr_target, rnd=bf16_round, rnd_act=None):
+    """Gradients of `loss` with the weights rounded by `rnd` as in forward_stored and the stored
+    back-propagated deltas (output delta, two hidden deltas) rounded by `rnd_act` (default `rnd`)."""
+    ra = rnd if rnd_act is None else rnd_act
     X, h1, a1, h2, a2 = cache
     B, m = out.shape
-    d_out = rnd((sigmoid(out) - sigmoid(llr_target)) / (B * m))
+    d_out = ra((sigmoid(out) - sigmoid(llr_target)) / (B * m))
     g = {"W3": a2.T @ d_out, "b3": d_out.sum(axis=0)}
-    d_h2 = rnd((d_out @ rnd(w["W3"]).T) * gelu_grad(h2))
+    d_h2 = ra((d_out @ rnd(w["W3"]).T) * gelu_grad(h2))
     g["W2"] = a1.T @ d_h2
     g["b2"] = d_h2.sum(axis=0)
-    d_h1 = rnd((d_h2 @ rnd(w["W2"]).T) * gelu_grad(h1))
+    d_h1 = ra((d_h2 @ rnd(w["W2"]).T) * gelu_grad(h1))
     g["W1"] = X.T @ d_h1
     g["b1"] = d_h1.sum(axis=0)
     return g

@@ -22,14 +22,14 @@ int dm_hard_decision(const dm_constellation* cc, int n_blk, const float* const* 
     if (n_blk < 1) return fail(DM_EINVAL, "n_blk=%d < 1", n_blk);
     if (N < 0 || N >= (int64_t(1) << 31)) return fail(DM_EINVAL, "N=%lld out of range", (long long)N);
     const bool counting = sym_err || bit_err;
-    if (counting && !tx) return fail(DM_EINVAL, "error counts need the transmitted rows (tx)");
-    if (N == 0) {
+    if (N == 0) {  // no symbols: nothing to read (empty device buffers may be null)
         for (int s = 0; s < n_blk; ++s) {
             if (sym_err) sym_err[s] = 0;
             if (bit_err) bit_err[s] = 0;
         }
         return DM_OK;
     }
+    if (counting && !tx) return fail(DM_EINVAL, "error counts need the transmitted rows (tx)");
     int r;
     if ((r = dmapi::check_current_device(c))) return r;
     if (counting && (r = dmapi::check_device_ptr(tx, "tx", c->device))) return r;
