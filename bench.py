@@ -35,6 +35,29 @@ FULL_RATE = CUS * SIMDS * LANES * CLOCK
 EXP2_ISSUE_CYCLES = 2  # v_exp_f32 issues at half the full FP32 rate on gfx950 (measured, see probe)
 
 
+# HBM bytes per launch of the headline kernel (fp16x3 MFMA demapper, 8D M=2048, 2^28 symbols)
+# from two rocprofv3 PMC passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors read off a
+# 512 MiB device copy in the same runs.  Valid only for the kernel sources they were taken on.
+TRAFFIC_PMC = {
+    "prec": "fp16x3", "workload": "gauss8d2048",
+    "bytes": (4463814 * 2 + 11542096) * 1024,
+    "sources": ["paper_2108_07004_amd/csrc/demap_mfma.hip", "paper_2108_07004_amd/csrc/mfma_body.hpp",
+                "paper_2108_07004_amd/csrc/device_common.hpp"],
+    "sha256": "848f4caf3bc27d9b2937ecabd24ac3f268aee2d015cfe5d8ec3d15f2167009d1",
+}
+
+
+def measured_traffic(prec, workload):
+    """Counter-measured HBM bytes per launch, or None when the kernel changed since or differs."""
+    import hashlib
+    if prec != TRAFFIC_PMC["prec"] or workload != TRAFFIC_PMC["workload"]:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_PMC["sources"]:
+        h.update((ROOT / f).read_bytes())
+    return float(TRAFFIC_PMC["bytes"]) if h.hexdigest() == TRAFFIC_PMC["sha256"] else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -265,7 +288,7 @@ def main():
     peak = FULL_RATE / EXP2_ISSUE_CYCLES
     achieved = exp2_per_launch / kern_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Texp2/s",
-            "frac": achieved / peak, "traffic": None}
+            "frac": achieved / peak, "traffic": measured_traffic(args.prec, w.name)}
 
     out = {
         "metric": METRIC,

@@ -546,17 +546,20 @@ int dm_demap_learned(dm_mlp* n, const dm_constellation* cc, int n_snr, const dou
     }
     const bool audit = tx && o.max_gmi_loss >= 0.0;
     const int64_t na = audit ? std::min<int64_t>(N, std::max<int64_t>((N + (int64_t(1) << o.audit_log2) - 1) >> o.audit_log2, 8192)) : 0;
-    // 2. learned inference for covered points: GMI of the audit prefix and of the rest kept apart
+    // 2. the network on the audit prefix [0, na) of every covered point (accumulator set 0); the
+    //    rest [na, N) runs only for the points that pass (set 1), so a failed audit costs 1/64.
     if (n->acc_snr < n_snr) {
         if ((r = dev_alloc(n->acc, (size_t)n_snr * 2 * dm::kAccSlots * 2, "GMI accumulators"))) return r;
         n->acc_snr = n_snr;
     }
-    if ((r = host_stage(n, (size_t)n_snr * 2 * dm::kAccSlots * 2 * sizeof(unsigned long long) + 64))) return r;
+    const size_t acc_words = (size_t)n_snr * 2 * dm::kAccSlots * 2;
+    if ((r = host_stage(n, acc_words * sizeof(unsigned long long) + 64))) return r;
     if ((r = ensure_packed(n, st))) return r;
-    DM_HIP_TRY(hipMemsetAsync(n->acc, 0, (size_t)n_snr * 2 * dm::kAccSlots * 2 * sizeof(unsigned long long), st));
+    DM_HIP_TRY(hipMemsetAsync(n->acc, 0, acc_words * sizeof(unsigned long long), st));
     DM_HIP_TRY(hipMemsetAsync(n->bad, 0, sizeof(uint32_t), st));
-    for (int s = 0; s < n_snr; ++s) {
-        if (code[s] != DM_LEARNED_OK) continue;
+    auto infer = [&](int s, int64_t lo, int64_t hi, int set) -> int {
+        const int64_t cnt = hi - lo;
+        if (cnt <= 0) return DM_OK;
         dm::MlpInferArgs a;
         std::memset(&a, 0, sizeof a);
         a.frag = n->frag;
@@ -567,34 +570,36 @@ int dm_demap_learned(dm_mlp* n, const dm_constellation* cc, int n_snr, const dou
         a.M = c->M;
         a.snr_feature = (float)((snr_db_of(sigma2[s]) - 7.5) / 7.5);
         a.bad_tx = tx ? n->bad : nullptr;
-        const int64_t parts[2][2] = {{0, audit ? na : 0}, {audit ? na : 0, N}};
-        for (int w = 0; w < 2; ++w) {
-            const int64_t lo = parts[w][0], cnt = parts[w][1] - parts[w][0];
-            if (cnt <= 0) continue;
-            a.y = y[s] + lo * n->D;
-            a.tx = tx ? tx + lo : nullptr;
-            a.llr = llr ? llr[s] + lo * n->m : nullptr;
-            a.N = cnt;
-            a.acc = tx ? n->acc + ((size_t)s * 2 + w) * dm::kAccSlots * 2 : nullptr;
-            const int64_t tiles = (cnt + 31) / 32;
-            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 7) / 8, n->cus));
-            DM_HIP_TRY(dm::launch_mlp_infer(a, grid, st));
-        }
-    }
+        a.y = y[s] + lo * n->D;
+        a.tx = tx ? tx + lo : nullptr;
+        a.llr = llr ? llr[s] + lo * n->m : nullptr;
+        a.N = cnt;
+        a.acc = tx ? n->acc + ((size_t)s * 2 + set) * dm::kAccSlots * 2 : nullptr;
+        const int64_t tiles = (cnt + 31) / 32;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((tiles + 7) / 8, n->cus));
+        DM_HIP_TRY(dm::launch_mlp_infer(a, grid, st));
+        return DM_OK;
+    };
     auto* acc_h = (unsigned long long*)n->h_stage;
-    auto* bad_h = (uint32_t*)(acc_h + (size_t)n_snr * 2 * dm::kAccSlots * 2);
-    DM_HIP_TRY(hipMemcpyAsync(acc_h, n->acc, (size_t)n_snr * 2 * dm::kAccSlots * 2 * sizeof(unsigned long long),
-                              hipMemcpyDeviceToHost, st));
-    DM_HIP_TRY(hipMemcpyAsync(bad_h, n->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    // 3. exact audit of the prefix (one launch over all audited points; synchronises)
+    auto* bad_h = (uint32_t*)(acc_h + acc_words);
+    auto slot_sum = [&](int s, int set) {
+        long long v = 0;
+        for (int k = 0; k < dm::kAccSlots; ++k) v += (long long)acc_h[(((size_t)s * 2 + set) * dm::kAccSlots + k) * 2];
+        return (double)v / dm::kFixScale;
+    };
+    for (int s = 0; s < n_snr; ++s) {
+        if (gmi_loss) gmi_loss[s] = NAN;
+        if (code[s] == DM_LEARNED_OK && audit && (r = infer(s, 0, na, 0))) return r;
+    }
+    // 3. exact audit of the prefixes (one launch over all audited points; synchronises)
     std::vector<int> aud;
     for (int s = 0; s < n_snr; ++s)
         if (code[s] == DM_LEARNED_OK && audit) aud.push_back(s);
-    std::vector<double> g_exact_prefix(n_snr, NAN);
     if (!aud.empty()) {
-        std::vector<double> s2;
+        DM_HIP_TRY(hipMemcpyAsync(acc_h, n->acc, acc_words * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        DM_HIP_TRY(hipMemcpyAsync(bad_h, n->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        std::vector<double> s2, g(aud.size());
         std::vector<const float*> ys;
-        std::vector<double> g(aud.size());
         for (int s : aud) {
             s2.push_back(sigma2[s]);
             ys.push_back(y[s]);
@@ -602,29 +607,28 @@ int dm_demap_learned(dm_mlp* n, const dm_constellation* cc, int n_snr, const dou
         if ((r = dmapi::gmi_run(c, (int)aud.size(), s2.data(), ys.data(), tx, na, nullptr, g.data(), nullptr,
                                 o.exact_prec, st)))
             return r;
-        for (size_t i = 0; i < aud.size(); ++i) g_exact_prefix[aud[i]] = g[i];
-    } else {
-        DM_HIP_TRY(hipStreamSynchronize(st));
+        if (*bad_h) return fail(DM_EINVAL, "a transmitted index is >= M");
+        for (size_t i = 0; i < aud.size(); ++i) {
+            const int s = aud[i];
+            const double loss_est = g[i] - slot_sum(s, 0) / (double)na;
+            if (gmi_loss) gmi_loss[s] = loss_est;
+            if (loss_est > o.max_gmi_loss) code[s] = DM_FALLBACK_AUDIT;
+        }
     }
+    // 4. the network on the rest of every point it keeps; exact over whole blocks elsewhere
+    for (int s = 0; s < n_snr; ++s)
+        if (code[s] == DM_LEARNED_OK && (r = infer(s, audit ? na : 0, N, 1))) return r;
+    DM_HIP_TRY(hipMemcpyAsync(acc_h, n->acc, acc_words * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    DM_HIP_TRY(hipMemcpyAsync(bad_h, n->bad, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    DM_HIP_TRY(hipStreamSynchronize(st));
     if (tx && *bad_h) return fail(DM_EINVAL, "a transmitted index is >= M");
-    auto slot_sum = [&](int s, int w) {
-        long long v = 0;
-        for (int k = 0; k < dm::kAccSlots; ++k) v += (long long)acc_h[(((size_t)s * 2 + w) * dm::kAccSlots + k) * 2];
-        return (double)v / dm::kFixScale;
-    };
-    // 4. decide per point; exact over the whole block where the network is not used
     std::vector<int> exact_pts;
     for (int s = 0; s < n_snr; ++s) {
-        if (gmi_loss) gmi_loss[s] = NAN;
         if (code[s] == DM_LEARNED_OK) {
             if (tx) gmi[s] = (slot_sum(s, 0) + slot_sum(s, 1)) / (double)N;
-            if (audit) {
-                const double loss_est = g_exact_prefix[s] - slot_sum(s, 0) / (double)na;
-                if (gmi_loss) gmi_loss[s] = loss_est;
-                if (loss_est > o.max_gmi_loss) code[s] = DM_FALLBACK_AUDIT;
-            }
+        } else {
+            exact_pts.push_back(s);
         }
-        if (code[s] != DM_LEARNED_OK) exact_pts.push_back(s);
     }
     if (!exact_pts.empty()) {
         std::vector<double> s2, g(exact_pts.size());

@@ -25,6 +25,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kH = 256;
 constexpr int kThreads = 512;   // 8 waves; one block per CU (the weights fill the LDS)
+constexpr int kRing = 4;        // layer-2 weight fragments in flight per wave
 constexpr int kW1Frags = 8 * 64;        // [block][lane]
 constexpr int kW2Frags = 8 * 16 * 64;   // [block][kstep][lane]
 constexpr int kW3Frags = 16 * 64;       // [kstep][lane]
@@ -38,10 +39,12 @@ __device__ __forceinline__ int perm_unit(int b, int i) {
     return 32 * b + 16 * (r >> 3) + 8 * h + (r & 7);
 }
 
-// tanh-form GELU, 0.5 x (1 + tanh(u)) = x / (1 + exp(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3)
+// tanh-form GELU, 0.5 x (1 + tanh(u)) = x / (1 + exp(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3).
+// exp(-2u) = 2^(x (c0 + c1 x^2)) with c0 = -2 sqrt(2/pi) log2(e), c1 = 0.044715 c0: three
+// multiply-adds, exp2, add, reciprocal, multiply per element.
 __device__ __forceinline__ float gelu_f(float x) {
-    const float u2 = 1.5957691216057308f * x * fmaf(0.044715f, x * x, 1.0f);
-    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * u2));
+    const float t = fmaf(-0.10294324f, x * x, -2.3022082f);
+    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * t));
 }
 
 // Fragment table from row-major (out x in) BF16 weights: W1t [256 x 32] (inputs 0..13 used),
@@ -120,14 +123,38 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
             for (int r = 0; r < 16; ++r) a1[2 * b + (r >> 3)][r & 7] = (__bf16)gelu_f(acc[r]);
         }
         f32x16 acc3 = {};
+        // Layer-2 weight fragments stream through a ring of kRing registers: the read of
+        // fragment g + kRing is issued right after fragment g is consumed, so LDS latency
+        // overlaps kRing - 1 MFMAs (the ring runs on across blocks; past the end it rereads the
+        // last fragment, which is never used).
+        bf16x8 ring[kRing];
+#pragma unroll
+        for (int q = 0; q < kRing; ++q) ring[q] = __builtin_bit_cast(bf16x8, w2[q * 64 + lane]);
 #pragma unroll 1
         for (int b = 0; b < 8; ++b) {
             f32x16 acc2 = {};
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks)
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w2[(b * 16 + ks) * 64 + lane]),
-                                                             a1[ks], acc2, 0, 0, 0);
-            const float* bb = lbias + (b * 2 + h) * 16;
+            for (int ks = 0; ks < 16; ++ks) {
+                const bf16x8 cur = ring[ks % kRing];
+                const int next = min(b * 16 + ks + kRing, 8 * 16 - 1);
+                ring[ks % kRing] = __builtin_bit_cast(bf16x8, w2[next * 64 + lane]);
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur, a1[ks], acc2, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);  // keep the read kRing steps ahead of its use
+            }
+            // block b's biases and layer-3 fragments, read together (one LDS wait)
+            const float4* bb4 = reinterpret_cast<const float4*>(lbias + (b * 2 + h) * 16);
+            float bb[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = bb4[q];
+                bb[4 * q] = v.x;
+                bb[4 * q + 1] = v.y;
+                bb[4 * q + 2] = v.z;
+                bb[4 * q + 3] = v.w;
+            }
+            const bf16x8 w3lo = __builtin_bit_cast(bf16x8, w3[(2 * b) * 64 + lane]);
+            const bf16x8 w3hi = __builtin_bit_cast(bf16x8, w3[(2 * b + 1) * 64 + lane]);
+            __builtin_amdgcn_sched_barrier(0);
             bf16x8 lo, hi;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -135,10 +162,8 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
                 if (r < 8) lo[r] = q;
                 else hi[r - 8] = q;
             }
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w3[(2 * b) * 64 + lane]), lo, acc3,
-                                                         0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w3[(2 * b + 1) * 64 + lane]), hi,
-                                                         acc3, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3lo, lo, acc3, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3hi, hi, acc3, 0, 0, 0);
         }
         // outputs: register r holds output o = 8 (r / 4) + 4 h + (r % 4) of symbol n
         int txl = 0;
