@@ -247,71 +247,92 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     const float (&accC)[4] = A.accC;
     const float (&hi0)[7] = A.hi0;
     const float (&hi1)[7] = A.hi1;
-    // Per-half marginals, then combine the two lanes (l, l^32) of each symbol.
+    // Per-half subset sums of every label bit, then combine the two lanes (l, l^32) of each
+    // symbol.  Bits 0-3 index the 16 registers: their marginals share one pairwise tree
+    // (P: pairs over bit 0, Q: pairs of P over bit 1); bit 4 is the lane half; bits 5-6 and
+    // 7-8 index accB and accC; higher bits were summed per 512-label block.
+    float P[8], Q[4];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) P[q] = accA[2 * q] + accA[2 * q + 1];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Q[u] = P[2 * u] + P[2 * u + 1];
     float S0[16], S1[16];
-    float tot = 0.0f;
+    S0[0] = ((accA[0] + accA[2]) + (accA[4] + accA[6])) + ((accA[8] + accA[10]) + (accA[12] + accA[14]));
+    S1[0] = ((accA[1] + accA[3]) + (accA[5] + accA[7])) + ((accA[9] + accA[11]) + (accA[13] + accA[15]));
+    S0[1] = (P[0] + P[2]) + (P[4] + P[6]);
+    S1[1] = (P[1] + P[3]) + (P[5] + P[7]);
+    S0[2] = Q[0] + Q[2];
+    S1[2] = Q[1] + Q[3];
+    S0[3] = Q[0] + Q[1];
+    S1[3] = Q[2] + Q[3];
+    const float tot = S0[3] + S1[3];
+    S0[4] = h ? 0.0f : tot;
+    S1[4] = h ? tot : 0.0f;
+    S0[5] = accB[0] + accB[2];
+    S1[5] = accB[1] + accB[3];
+    S0[6] = accB[0] + accB[1];
+    S1[6] = accB[2] + accB[3];
+    S0[7] = accC[0] + accC[2];
+    S1[7] = accC[1] + accC[3];
+    S0[8] = accC[0] + accC[1];
+    S1[8] = accC[2] + accC[3];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) tot += accA[r];
-#pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        float s0 = 0.0f, s1 = 0.0f;
-        if (p < 4) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                if ((r >> p) & 1) s1 += accA[r];
-                else s0 += accA[r];
-            }
-        } else if (p == 4) {
-            s0 = h ? 0.0f : tot;
-            s1 = h ? tot : 0.0f;
-        } else if (p < 7) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if ((u >> (p - 5)) & 1) s1 += accB[u];
-                else s0 += accB[u];
-            }
-        } else if (p < 9) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if ((q >> (p - 7)) & 1) s1 += accC[q];
-                else s0 += accC[q];
-            }
-        } else {
-            s0 = hi0[p - 9];
-            s1 = hi1[p - 9];
-        }
-        S0[p] = s0;
-        S1[p] = s1;
+    for (int p = 9; p < 16; ++p) {
+        S0[p] = hi0[p - 9];
+        S1[p] = hi1[p - 9];
     }
+    // Exchange with the partner lane: half h keeps bit 2j + h of every pair (2j, 2j+1) and
+    // sends the partner its partial sums of the other bit.
+    float c0[8], c1[8];
 #pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        if (p < m) {
-            S0[p] += __shfl_xor(S0[p], 32, 64);
-            S1[p] += __shfl_xor(S1[p], 32, 64);
+    for (int j = 0; j < 8; ++j) {
+        if (2 * j < m) {
+            const float o0 = h ? S0[2 * j + 1] : S0[2 * j], o1 = h ? S1[2 * j + 1] : S1[2 * j];
+            const float x0 = h ? S0[2 * j] : S0[2 * j + 1], x1 = h ? S1[2 * j] : S1[2 * j + 1];
+            c0[j] = o0 + __shfl_xor(x0, 32, 64);
+            c1[j] = o1 + __shfl_xor(x1, 32, 64);
         }
     }
     const bool bad_sym = bad || __shfl_xor((int)bad, 32, 64);
-    const float stot = S0[0] + S1[0];
+    const float stot = tot + __shfl_xor(tot, 32, 64);
 
     const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
     g = 0.0f;
     uint32_t mask = 0;
     float* out = (b.llr && active) ? b.llr + (size_t)n * m : nullptr;
+    // Lane half h finishes bits p = 2j + h: the same j for both halves keeps the control flow
+    // uniform, so every bit is processed once per wave.
+    uint32_t flagged = 0;
 #pragma unroll
-    for (int p = 0; p < 16; ++p) {
-        if (p < m && (p & 1) == h) {
-            const float s0 = S0[p], s1 = S1[p];
-            const bool flagged = bad_sym || !(fminf(s0, s1) >= b.flag_thresh) || !(fmaxf(s0, s1) < 3.0e38f);
-            const float L = log2_ratio(s1, s0);
-            const int bit = (txl >> p) & 1;
-            if (!flagged) {
-                if (out) out[m - 1 - p] = L * 0.69314718055994531f;
-                g += gmi_bit_term(L, bit);
-            } else if (!bad_sym && !b.want_llr && fmaxf(s0, s1) >= b.near_thresh &&
-                       fmaxf(s0, s1) < 3.0e38f && (bit ? s1 > s0 : s0 > s1)) {
-                g += 1.0f;
-            } else {
-                mask |= 1u << p;
+    for (int j = 0; j < 8; ++j) {
+        if (2 * j < m) {
+            const int p = 2 * j + h;
+            const float s0 = c0[j], s1 = c1[j];
+            if (p < m) {
+                if (!bad_sym && fminf(s0, s1) >= b.flag_thresh && fmaxf(s0, s1) < 3.0e38f) {
+                    const float L = log2_ratio(s1, s0);
+                    if (out) out[m - 1 - p] = L * 0.69314718055994531f;
+                    g += gmi_bit_term(L, (txl >> p) & 1);
+                } else {
+                    flagged |= 1u << p;
+                }
+            }
+        }
+    }
+    if (flagged) {  // rare: the GMI-only shortcut, else the exact fix-up
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (2 * j < m) {
+                const int p = 2 * j + h;
+                const float s0 = c0[j], s1 = c1[j];
+                if ((flagged >> p) & 1) {
+                    const int bit = (txl >> p) & 1;
+                    if (!bad_sym && !b.want_llr && fmaxf(s0, s1) >= b.near_thresh && fmaxf(s0, s1) < 3.0e38f &&
+                        (bit ? s1 > s0 : s0 > s1))
+                        g += 1.0f;
+                    else
+                        mask |= 1u << p;
+                }
             }
         }
     }
