@@ -1,9 +1,12 @@
 // Batched exact demapping: one persistent launch over many (constellation, noise level, block)
 // instances of uneven M, D and N (gfx950).
 //
-// Work items are (instance, symbol tile) pairs listed instance by instance; the host cuts the
-// list into one contiguous, cost-balanced segment per workgroup, so a workgroup restages its
-// LDS table only when its segment crosses into the next instance.  Each instance runs either
+// Work items are (instance, symbol tile) pairs listed instance by instance, the most costly
+// instance first.  Workgroups claim fixed chunks of `grab` consecutive items from a counter
+// (dynamic balance: the cheap items at the end fill the tail) and restage their LDS table only
+// when the next item belongs to another instance.  GMI / MI partial sums are flushed per chunk
+// and instance, so every fixed-point contribution covers a fixed set of symbols whichever
+// workgroup runs it: the totals are bit-reproducible.  Each instance runs either
 // the FP32 direct-difference body (one lane per symbol, 1024-symbol tiles) or the MFMA body
 // (one wave per 32 symbols, 512-symbol tiles), as chosen per (M, D) by the autotuner.  Batched
 // tables use a row stride of 8 (D <= 8 zero-padded): the padded coordinates contribute exact
@@ -28,71 +31,80 @@ __global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs
     const int lane = tid & 63;
     const int h = lane >> 5;
     const int wave = tid >> 6;
-    const int wave_slot = (blockIdx.x * kWaves + wave) % kAccSlots;
+    const int wave_slot = (blockIdx.x * kWaves + wave) % kAccSlots;  // integer slots: any spread sums alike
     const Sinks& k = a.sinks;
-    const int i0 = a.seg[blockIdx.x], i1 = a.seg[blockIdx.x + 1];
-    int staged = -1, cur = -1;
-    double gsum = 0.0, msum = 0.0;
-    for (int i = i0; i < i1; ++i) {
-        const WorkItem it = a.items[i];
-        const int inst = it.inst;
-        const BatchDesc& d = a.desc[inst];
-        const BlockView b = d.view;
-        const int kind = d.kind;
-        if (inst != staged) {  // restage the point table (whole block, uniform condition)
-            __syncthreads();
+    __shared__ int s_claim;
+    int staged = -1;
+    for (;;) {
+        if (tid == 0) s_claim = (int)atomicAdd(a.next, (uint32_t)a.grab);
+        __syncthreads();
+        const int i0 = s_claim;
+        __syncthreads();  // every thread has read the claim before it is overwritten
+        if (i0 >= a.n_items) break;
+        const int i1 = min(i0 + a.grab, a.n_items);
+        int cur = -1;
+        double gsum = 0.0, msum = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const WorkItem it = a.items[i];
+            const int inst = it.inst;
+            const BatchDesc& d = a.desc[inst];
+            const BlockView b = d.view;
+            const int kind = d.kind;
+            if (inst != staged) {  // restage the point table (whole block, uniform condition)
+                __syncthreads();
+                if (kind == kKindMfma) {
+                    const int n16 = (b.M >> 5) * S * 64;
+                    for (int j = tid; j < n16; j += kThreads) lds_raw[j] = d.frag[j];
+                } else {
+                    float* lds = reinterpret_cast<float*>(lds_raw);
+                    const int Mpad = b.M < 16 ? 16 : b.M;
+                    for (int j = tid; j < Mpad * 8; j += kThreads)
+                        lds[j] = (j < b.M * 8) ? b.table[j] : 1.0e19f;  // padding rows: e_j = 0
+                }
+                __syncthreads();
+                staged = inst;
+            }
+            if (inst != cur) {
+                if (cur >= 0 && k.acc && lane == 0) {
+                    acc_add(k.acc, cur, wave_slot, 0, gsum);
+                    acc_add(k.acc, cur, wave_slot, 1, msum);
+                }
+                gsum = msum = 0.0;
+                cur = inst;
+            }
+            float g = 0.0f, mi = 0.0f;
+            bool active;
             if (kind == kKindMfma) {
-                const int n16 = (b.M >> 5) * S * 64;
-                for (int j = tid; j < n16; j += kThreads) lds_raw[j] = d.frag[j];
+                const int64_t n = it.n0 + wave * 32 + (lane & 31);
+                active = n < b.N;
+                float y[8];
+                load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
+                bool bad = false;
+                const Frags<T, S> bfr = build_symbol_frags<T, 8, SPLIT>(y, b.c, b.K, h, bad);
+                MfmaAcc A;
+                A.init();
+                mfma_tiles<T, 8, SPLIT>(lds_raw, lane, 0, b.M >> 5, b.m, bfr, A);
+                mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, lane, g, mi);
             } else {
-                float* lds = reinterpret_cast<float*>(lds_raw);
+                const int64_t n = it.n0 + tid;
+                active = n < b.N;
+                float y[8];
+                load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
+                DM_VALU_ACC_DECL
                 const int Mpad = b.M < 16 ? 16 : b.M;
-                for (int j = tid; j < Mpad * 8; j += kThreads)
-                    lds[j] = (j < b.M * 8) ? b.table[j] : 1.0e19f;  // padding rows: e_j = 0
+                valu_accumulate<8>(reinterpret_cast<const float*>(lds_raw), 0, Mpad, y, b.c, b.K, b.m, accA, accB,
+                                   hi0, hi1);
+                valu_epilogue<8>(b, k, n, active, y, accA, accB, hi0, hi1, g, mi);
             }
-            __syncthreads();
-            staged = inst;
-        }
-        if (inst != cur) {
-            if (cur >= 0 && k.acc && lane == 0) {
-                acc_add(k.acc, cur, wave_slot, 0, gsum);
-                acc_add(k.acc, cur, wave_slot, 1, msum);
+            if (k.acc) {
+                gsum += wave_sum(active ? (double)g : 0.0);
+                msum += wave_sum(active ? (double)mi : 0.0);
             }
-            gsum = msum = 0.0;
-            cur = inst;
         }
-        float g = 0.0f, mi = 0.0f;
-        bool active;
-        if (kind == kKindMfma) {
-            const int64_t n = it.n0 + wave * 32 + (lane & 31);
-            active = n < b.N;
-            float y[8];
-            load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
-            bool bad = false;
-            const Frags<T, S> bfr = build_symbol_frags<T, 8, SPLIT>(y, b.c, b.K, h, bad);
-            MfmaAcc A;
-            A.init();
-            mfma_tiles<T, 8, SPLIT>(lds_raw, lane, 0, b.M >> 5, b.m, bfr, A);
-            mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, lane, g, mi);
-        } else {
-            const int64_t n = it.n0 + tid;
-            active = n < b.N;
-            float y[8];
-            load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
-            DM_VALU_ACC_DECL
-            const int Mpad = b.M < 16 ? 16 : b.M;
-            valu_accumulate<8>(reinterpret_cast<const float*>(lds_raw), 0, Mpad, y, b.c, b.K, b.m, accA, accB, hi0,
-                               hi1);
-            valu_epilogue<8>(b, k, n, active, y, accA, accB, hi0, hi1, g, mi);
+        if (cur >= 0 && k.acc && lane == 0) {
+            acc_add(k.acc, cur, wave_slot, 0, gsum);
+            acc_add(k.acc, cur, wave_slot, 1, msum);
         }
-        if (k.acc) {
-            gsum += wave_sum(active ? (double)g : 0.0);
-            msum += wave_sum(active ? (double)mi : 0.0);
-        }
-    }
-    if (cur >= 0 && k.acc && lane == 0) {
-        acc_add(k.acc, cur, wave_slot, 0, gsum);
-        acc_add(k.acc, cur, wave_slot, 1, msum);
     }
 }
 

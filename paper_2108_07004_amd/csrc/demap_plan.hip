@@ -27,6 +27,7 @@ using namespace dmapi;
 namespace {
 
 constexpr int kProbeSymbols = 32768;  // symbols timed per autotune candidate
+constexpr int kGrab = 4;              // work items per claim of a workgroup
 
 struct TuneKey {
     int M, D, prec, kind;
@@ -93,7 +94,6 @@ struct dm_plan {
     std::vector<double> ns_per_pair;
     dm::BatchDesc* d_desc = nullptr;
     dm::WorkItem* d_items = nullptr;
-    int32_t* d_seg = nullptr;
     uint32_t* d_words = nullptr;  // acc (2 words per int64) | fix_pairs[n] | bad_tx | queue_count
     size_t n_words = 0;
     dm::FixEntry* d_queue = nullptr;
@@ -142,39 +142,29 @@ int build_descs(dm_plan* p, std::vector<dm::BatchDesc>& desc) {
     return DM_OK;
 }
 
-// Work list in instance order and its contiguous split into `grid` cost-balanced segments.
-void build_work(const dm_plan* p, std::vector<dm::WorkItem>& items, std::vector<int32_t>& seg, int grid) {
-    std::vector<double> cost;
+// Work list: instances in decreasing order of estimated cost (ns per pair x M x N), each as
+// consecutive symbol tiles.  Workgroups claim it in chunks at run time.
+void build_work(const dm_plan* p, std::vector<dm::WorkItem>& items) {
+    std::vector<int> order(p->n_inst);
+    std::vector<double> cost(p->n_inst);
     for (int i = 0; i < p->n_inst; ++i) {
-        const int tile = dm::batched_tile_symbols(p->kind[i]);
-        const double per = p->ns_per_pair[i] * p->inst[i].c->M;
-        for (int64_t n0 = 0; n0 < p->inst[i].N; n0 += tile) {
-            items.push_back(dm::WorkItem{i, 0, n0});
-            cost.push_back(per * (double)std::min<int64_t>(tile, p->inst[i].N - n0));
-        }
+        order[i] = i;
+        cost[i] = p->ns_per_pair[i] * p->inst[i].c->M * (double)p->inst[i].N;
     }
-    double total = 0.0;
-    for (double v : cost) total += v;
-    seg.assign(grid + 1, (int32_t)items.size());
-    seg[0] = 0;
-    double acc = 0.0;
-    int g = 1;
-    for (size_t j = 0; j < items.size() && g < grid; ++j) {
-        acc += cost[j];
-        while (g < grid && acc >= total * g / grid) seg[g++] = (int32_t)(j + 1);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int i : order) {
+        const int tile = dm::batched_tile_symbols(p->kind[i]);
+        for (int64_t n0 = 0; n0 < p->inst[i].N; n0 += tile) items.push_back(dm::WorkItem{i, 0, n0});
     }
 }
 
-int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const std::vector<dm::WorkItem>& items,
-                       const std::vector<int32_t>& seg) {
+int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const std::vector<dm::WorkItem>& items) {
     DM_HIP_TRY(hipMalloc(&p->d_desc, desc.size() * sizeof(dm::BatchDesc)));
     DM_HIP_TRY(hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(dm::WorkItem)));
-    DM_HIP_TRY(hipMalloc(&p->d_seg, seg.size() * sizeof(int32_t)));
     DM_HIP_TRY(hipMemcpy(p->d_desc, desc.data(), desc.size() * sizeof(dm::BatchDesc), hipMemcpyHostToDevice));
     if (!items.empty())
         DM_HIP_TRY(hipMemcpy(p->d_items, items.data(), items.size() * sizeof(dm::WorkItem), hipMemcpyHostToDevice));
-    DM_HIP_TRY(hipMemcpy(p->d_seg, seg.data(), seg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    p->n_words = (size_t)p->n_inst * dm::kAccSlots * 2 * 2 + p->n_inst + 2;
+    p->n_words = (size_t)p->n_inst * dm::kAccSlots * 2 * 2 + p->n_inst + 3;
     DM_HIP_TRY(hipMalloc(&p->d_words, p->n_words * sizeof(uint32_t)));
     int64_t total_n = 0;
     for (const auto& in : p->inst) total_n += in.N;
@@ -185,7 +175,9 @@ int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const
     uint32_t* tail = p->d_words + (size_t)p->n_inst * dm::kAccSlots * 2 * 2;
     p->args.desc = p->d_desc;
     p->args.items = p->d_items;
-    p->args.seg = p->d_seg;
+    p->args.n_items = (int32_t)items.size();
+    p->args.grab = kGrab;
+    p->args.next = tail + p->n_inst + 2;
     p->args.sinks.acc = acc;
     p->args.sinks.fix_pairs = tail;
     p->args.sinks.bad_tx = tail + p->n_inst;
@@ -209,7 +201,6 @@ void free_plan(dm_plan* p) {
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     (void)hipFree(p->d_desc);
     (void)hipFree(p->d_items);
-    (void)hipFree(p->d_seg);
     (void)hipFree(p->d_words);
     (void)hipFree(p->d_queue);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
@@ -235,7 +226,6 @@ int make_plan(const dm_instance* inst, int n_inst, int prec, const std::vector<i
     }
     std::vector<dm::BatchDesc> desc;
     std::vector<dm::WorkItem> items;
-    std::vector<int32_t> seg;
     int r = build_descs(p, desc);
     if (r) {
         free_plan(p);
@@ -248,8 +238,8 @@ int make_plan(const dm_instance* inst, int n_inst, int prec, const std::vector<i
         return hip_fail(e, "hipFuncSetAttribute(batched kernel)");
     }
     p->fix_grid = cus * 4;
-    build_work(p, items, seg, p->grid);
-    r = alloc_plan_buffers(p, desc, items, seg);
+    build_work(p, items);
+    r = alloc_plan_buffers(p, desc, items);
     if (r) {
         free_plan(p);
         return r;

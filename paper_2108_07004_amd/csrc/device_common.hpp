@@ -101,8 +101,10 @@ struct WorkItem {              // symbols [n0, n0 + tile) of one instance
 
 struct BatchArgs {
     const BatchDesc* desc;
-    const WorkItem* items;
-    const int32_t* seg;        // workgroup g processes items [seg[g], seg[g+1])
+    const WorkItem* items;     // instance by instance, largest instance cost first
+    int32_t n_items;
+    int32_t grab;              // items per claim; claims start at multiples of grab
+    uint32_t* next;            // claim counter (zeroed before every launch)
     Sinks sinks;
 };
 
