@@ -210,6 +210,28 @@ def bench_hard(const, w, ys, tx_t, steps):
             "q_db": [None if not (0 < b < 0.5) else round(dm.q_factor_db(float(b)), 3) for b in ber]}
 
 
+def bench_stream(const, w, ys, prec, buffer_symbols=1 << 20, n_buffers=3):
+    """Host-to-host streamed demapping of one received block (PCIe transfers included)."""
+    import paper_2108_07004_amd as dm
+
+    import torch
+
+    y = torch.empty((w.N, w.const.D), dtype=torch.float32, pin_memory=True)
+    y.copy_(ys[len(ys) // 2])
+    llr = torch.empty((w.N, w.const.m), dtype=torch.float32, pin_memory=True)
+    s2 = float(w.sigma2[len(ys) // 2])
+    st = dm.Streamer(const, buffer_symbols=buffer_symbols, n_buffers=n_buffers, prec=prec)
+    st.run(s2, y[: 4 * buffer_symbols], llr[: 4 * buffer_symbols])  # warm-up
+    _, sec = st.run(s2, y, llr)
+    st.close()
+    del y, llr
+    per_sym = 4 * (w.const.D + w.const.m)
+    return {"workload": f"{w.name}: one block of N={w.N} from pinned host memory, LLRs back to pinned host memory, "
+                        f"{buffer_symbols}-symbol buffers, {n_buffers} slots, {prec}",
+            "symbols_per_s": w.N / sec, "seconds": sec, "pcie_bytes_per_symbol": per_sym,
+            "pcie_GB_per_s": w.N * per_sym / sec / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +244,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip training + timing the learned demapper")
     ap.add_argument("--no-hard", action="store_true", help="skip the hard-decision measurement")
+    ap.add_argument("--no-stream", action="store_true", help="skip the host-to-host streamed measurement")
     ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
     ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -312,12 +335,18 @@ def main():
                    "probe_exp2_Tps": rates["exp2_per_s"] / 1e12, "probe_fma_Tps": rates["fma_per_s"] / 1e12,
                    "probe_exp2_add2_Tps": rates["exp2_add2_per_s"] / 1e12},
         "gmi": [round(float(v), 6) for v in gmi],
+        "ngmi": [round(float(v) / w.const.m, 6) for v in gmi],
     }
     if not args.no_batched:
         log("batched: 64 uneven instances, autotuned plan, graph replay")
         out["batched"] = bench_batched(args.prec if args.prec != "fp32" else "fp16x3", max(3, args.steps), 2)
         log(f"batched: {out['batched']['ms_per_launch']:.3f} ms/launch, "
             f"{out['batched']['symbols_per_s'] / 1e9:.3f} Gsym/s")
+    if not args.no_stream:
+        log("streamed: host buffers in, host LLRs out")
+        out["streamed"] = bench_stream(const, w, ys, args.prec)
+        log(f"streamed: {out['streamed']['symbols_per_s'] / 1e9:.3f} Gsym/s host to host, "
+            f"{out['streamed']['pcie_GB_per_s']:.1f} GB/s over PCIe")
     if not args.no_hard:
         log("hard decisions: minimum-distance labels + error counts")
         out["hard_decision"] = bench_hard(const, w, ys, tx_t, max(2, min(args.steps, 5)))

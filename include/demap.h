@@ -309,6 +309,24 @@ int dm_gs_optimize(const float* points, const uint16_t* labels, int32_t M, int32
                    const uint16_t* tx, const float* z, int64_t N, float* out_points, double* gmi_trace,
                    int32_t* accepted, void* stream);
 
+/*
+ * Streamed demapping of host-resident data (the paper's receiver handles fixed-size sample
+ * buffers as they arrive, Sec. 2): the host block is processed in buffers of buffer_symbols
+ * symbols cycling through n_buffers slots of pinned staging and device memory; each buffer's
+ * host-to-device copy, demapping and device-to-host copy run on three streams of default
+ * priority, so transfers of one buffer overlap the demapping of another.
+ * dm_streamer_run: y HOST N x D FP32 (any host memory; page-locked memory is transferred
+ * directly, other memory through the pinned staging), llr HOST N x m FP32 output (nats),
+ * seconds HOST wall time of the call or NULL.  Synchronous: returns when every LLR is in llr.
+ * LLRs are identical to dm_demap_llr on the whole block.  Limits: 1 <= buffer_symbols <= 2^26,
+ * 2 <= n_buffers <= 16.  Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_ENOMEM, DM_EHIP.
+ */
+typedef struct dm_streamer dm_streamer;
+int dm_streamer_create(const dm_constellation* c, int64_t buffer_symbols, int32_t n_buffers, int32_t prec,
+                       dm_streamer** out);
+int dm_streamer_run(dm_streamer* s, double sigma2, const float* y, int64_t N, float* llr, double* seconds);
+void dm_streamer_destroy(dm_streamer* s);
+
 /* Number of (symbol, bit) pairs that the last call on this thread sent through the
  * far-subset underflow fix-up, per SNR point (HOST array of n_snr, may be NULL).
  * Returns the total, or a negative DM_E* if no call has run on this thread. */

@@ -17,7 +17,7 @@ from typing import Sequence
 import numpy as np
 
 __all__ = ["Constellation", "DemapError", "MLP", "PREC", "Plan", "demap_batched", "demap_learned", "demap_llr",
-           "demap_llr_var", "gmi_estimate", "gs_optimize", "hard_decision", "q_factor_db", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
+           "demap_llr_var", "gmi_estimate", "gs_optimize", "hard_decision", "q_factor_db", "Streamer", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
            "probe_valu_rates", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
@@ -104,6 +104,12 @@ def load_library():
     lib.dm_q_factor_db.restype = D
     lib.dm_gs_optimize.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P, P, P, I64, P, P, P, P]
     lib.dm_gs_optimize.restype = I
+    lib.dm_streamer_create.argtypes = [P, I64, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.dm_streamer_create.restype = I
+    lib.dm_streamer_run.argtypes = [P, D, P, I64, P, P]
+    lib.dm_streamer_run.restype = I
+    lib.dm_streamer_destroy.argtypes = [P]
+    lib.dm_streamer_destroy.restype = None
     lib.dm_last_error.restype = ctypes.c_char_p
     lib.dm_version.restype = ctypes.c_char_p
     _lib = lib
@@ -550,3 +556,56 @@ def gs_optimize(points, labels, snr_db: float, tx, z, iters: int = 200, candidat
                                          trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(acc),
                                          _stream_handle(stream)))
     return out, np.arange(M, dtype=np.uint16), trace, int(acc.value)
+
+
+class Streamer:
+    """Streamed demapping of host arrays in fixed-size buffers (dm_streamer_*)."""
+
+    def __init__(self, const: Constellation, buffer_symbols: int = 1 << 20, n_buffers: int = 3, prec: str = "fp32"):
+        self.D, self.m = const.D, const.m
+        self._const = const
+        h = ctypes.c_void_p()
+        _check(load_library().dm_streamer_create(const.handle, int(buffer_symbols), int(n_buffers), PREC[prec],
+                                                 ctypes.byref(h)))
+        self._h = h
+
+    def run(self, sigma2: float, y, llr=None):
+        """Demap host y (N, D) FP32 into host llr (N, m) FP32; returns (llr, seconds).
+
+        y / llr may be NumPy arrays or CPU torch tensors (pinned tensors are transferred directly).
+        """
+        import torch
+        if isinstance(y, torch.Tensor) or isinstance(llr, torch.Tensor):
+            N = int(y.shape[0])
+            if llr is None:
+                llr = torch.empty((N, self.m), dtype=torch.float32, pin_memory=y.is_pinned())
+            for t, shp, nm in ((y, (N, self.D), "y"), (llr, (N, self.m), "llr")):
+                if t.is_cuda or t.dtype != torch.float32 or tuple(t.shape) != shp or not t.is_contiguous():
+                    raise ValueError(f"{nm} must be a contiguous float32 CPU tensor of shape {shp}")
+            sec = ctypes.c_double()
+            _check(load_library().dm_streamer_run(self._h, float(sigma2), ctypes.c_void_p(y.data_ptr()), N,
+                                                  ctypes.c_void_p(llr.data_ptr()), ctypes.byref(sec)))
+            return llr, sec.value
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        N = int(y.shape[0])
+        if y.shape != (N, self.D):
+            raise ValueError("y must be N x D")
+        if llr is None:
+            llr = np.empty((N, self.m), dtype=np.float32)
+        if llr.shape != (N, self.m) or llr.dtype != np.float32 or not llr.flags["C_CONTIGUOUS"]:
+            raise ValueError("llr must be a C-contiguous float32 N x m array")
+        sec = ctypes.c_double()
+        _check(load_library().dm_streamer_run(self._h, float(sigma2), y.ctypes.data_as(ctypes.c_void_p), N,
+                                              llr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sec)))
+        return llr, sec.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().dm_streamer_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

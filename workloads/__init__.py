@@ -133,6 +133,37 @@ def rect_qam(levels_i: int, levels_q: int, name: str = "") -> Constellation:
                          name or f"{levels_i * levels_q}-qam-rect")
 
 
+def cross_qam(M: int, name: str = "") -> Constellation:
+    """Cross QAM (M = 32 or 128): a square grid of odd integer amplitudes with the four corner
+    blocks removed (6 x 6 minus 4 corners for 32, 12 x 12 minus four 2 x 2 corners for
+    128), unit energy per 2D.  Labels are the raster index of the kept points (the paper's own
+    mappings are not published; any bijection is a valid labelling)."""
+    side, cut = {32: (6, 1), 128: (12, 2)}[M]
+    amps = 2 * np.arange(side) - (side - 1)
+    pts = []
+    for i in range(side):
+        for q in range(side):
+            corner = (i < cut or i >= side - cut) and (q < cut or q >= side - cut)
+            if not corner:
+                pts.append((amps[i], amps[q]))
+    p = np.asarray(pts, dtype=np.float64)
+    p *= math.sqrt(1.0 / float(np.mean(np.sum(p * p, axis=1))))
+    return Constellation(p.astype(np.float32), np.arange(M, dtype=np.uint16), name or f"{M}-qam-cross")
+
+
+def qam(M: int) -> Constellation:
+    """The paper's conventional 2D formats: 4-, 16-, 64-QAM square Gray, 8-QAM rectangular,
+    32- and 128-QAM cross."""
+    if M in (4, 16, 64, 256):
+        k = int(round(math.sqrt(M)))
+        return product_pam(k, 2, f"{M}-qam")
+    if M == 8:
+        return rect_qam(4, 2, "8-qam")
+    if M in (32, 128):
+        return cross_qam(M)
+    raise KeyError(M)
+
+
 def pam(levels: int) -> Constellation:
     """1D BRGC PAM (used by closed-form checks)."""
     return product_pam(levels, 1, f"{levels}-pam")
