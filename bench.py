@@ -179,11 +179,11 @@ def bench_learned(const, w, ys, tx_t, llrs, exact_gmi, exact_sym_per_s, exact_pr
     }
 
 
-FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (an FMA counts 2)
-
-
 def bench_hard(const, w, ys, tx_t, steps):
-    """Minimum-distance decisions of the headline block (labels written, symbol / bit errors counted)."""
+    """Minimum-distance decisions of the headline block (labels written, symbol / bit errors counted).
+
+    Priced per (symbol, point) pair against the vector-ALU issue rate (one lane-operation per
+    pair): the MFMA method ranks points with 4 integer max / min / insert operations per pair."""
     import torch
 
     import paper_2108_07004_amd as dm
@@ -195,41 +195,39 @@ def bench_hard(const, w, ys, tx_t, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        se, be = dm.hard_decision(const, ys, tx_t, outs)
+        se, be, nx = dm.hard_decision(const, ys, tx_t, outs, return_exact=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     n_sym = w.N * len(ys)
     pairs = float(n_sym) * w.const.M
-    flops = pairs * 3 * w.const.D  # per (symbol, point): D subtractions + D fused multiply-adds
     ber = be / (w.N * w.const.m)
     return {"workload": f"{w.name}: N={w.N} x {len(ys)} blocks, min-distance labels + symbol/bit error counts",
-            "symbols_per_s": n_sym / dt, "ms_per_step": dt * 1e3,
-            "roofline": {"bound": "alu", "achieved": flops / dt / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                         "unit": "TFLOP/s", "frac": flops / dt / FP32_VECTOR_PEAK, "traffic": None},
+            "symbols_per_s": n_sym / dt, "ms_per_step": dt * 1e3, "exact_path_symbols": nx,
+            "roofline": {"bound": "alu", "achieved": pairs / dt / 1e12, "peak": FULL_RATE / 1e12,
+                         "unit": "Tpairs/s", "frac": pairs / dt / FULL_RATE, "traffic": None},
             "ser": [float(v) / w.N for v in se], "ber": [float(v) for v in ber],
             "q_db": [None if not (0 < b < 0.5) else round(dm.q_factor_db(float(b)), 3) for b in ber]}
 
 
-def bench_stream(const, w, ys, prec, buffer_symbols=1 << 20, n_buffers=3):
-    """Host-to-host streamed demapping of one received block (PCIe transfers included)."""
-    import paper_2108_07004_amd as dm
-
+def bench_gs(iters=100, candidates=32, N=1 << 16):
+    """GMI-driven shaping search from rectangular 8-QAM at 14 dB (the paper's GS-8 design point)."""
     import torch
 
-    y = torch.empty((w.N, w.const.D), dtype=torch.float32, pin_memory=True)
-    y.copy_(ys[len(ys) // 2])
-    llr = torch.empty((w.N, w.const.m), dtype=torch.float32, pin_memory=True)
-    s2 = float(w.sigma2[len(ys) // 2])
-    st = dm.Streamer(const, buffer_symbols=buffer_symbols, n_buffers=n_buffers, prec=prec)
-    st.run(s2, y[: 4 * buffer_symbols], llr[: 4 * buffer_symbols])  # warm-up
-    _, sec = st.run(s2, y, llr)
-    st.close()
-    del y, llr
-    per_sym = 4 * (w.const.D + w.const.m)
-    return {"workload": f"{w.name}: one block of N={w.N} from pinned host memory, LLRs back to pinned host memory, "
-                        f"{buffer_symbols}-symbol buffers, {n_buffers} slots, {prec}",
-            "symbols_per_s": w.N / sec, "seconds": sec, "pcie_bytes_per_symbol": per_sym,
-            "pcie_GB_per_s": w.N * per_sym / sec / 1e9}
+    import paper_2108_07004_amd as dm
+    import workloads as W
+
+    c = W.rect_qam(4, 2)
+    g = W.rng(70, "misc", 0)
+    tx = torch.from_numpy(g.integers(0, 8, size=N).astype(np.int16)).cuda()
+    z = torch.from_numpy(g.standard_normal((N, 2)).astype(np.float32)).cuda()
+    dm.gs_optimize(c.points, c.labels, 14.0, tx, z, iters=2, candidates=candidates)  # warm-up
+    t0 = time.perf_counter()
+    _, _, trace, acc = dm.gs_optimize(c.points, c.labels, 14.0, tx, z, iters=iters, candidates=candidates, seed=7)
+    dt = time.perf_counter() - t0
+    evals = iters * candidates
+    return {"workload": f"8-QAM at 14 dB, {iters} iterations x {candidates} candidates, N={N} common block",
+            "seconds": dt, "candidate_evals_per_s": evals / dt, "symbols_per_s": evals * N / dt,
+            "gmi_start": round(float(trace[0]), 5), "gmi_end": round(float(trace[-1]), 5), "accepted": acc}
 
 
 def main():
@@ -245,6 +243,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip training + timing the learned demapper")
     ap.add_argument("--no-hard", action="store_true", help="skip the hard-decision measurement")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-to-host streamed measurement")
+    ap.add_argument("--no-gs", action="store_true", help="skip the shaping-search measurement")
     ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
     ap.add_argument("--learned-batch", type=int, default=4096)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -347,6 +346,11 @@ def main():
         out["streamed"] = bench_stream(const, w, ys, args.prec)
         log(f"streamed: {out['streamed']['symbols_per_s'] / 1e9:.3f} Gsym/s host to host, "
             f"{out['streamed']['pcie_GB_per_s']:.1f} GB/s over PCIe")
+    if not args.no_gs:
+        log("shaping search: 8-QAM at 14 dB")
+        out["gs_search"] = bench_gs()
+        log(f"shaping search: {out['gs_search']['candidate_evals_per_s']:.0f} candidates/s, GMI "
+            f"{out['gs_search']['gmi_start']} -> {out['gs_search']['gmi_end']}")
     if not args.no_hard:
         log("hard decisions: minimum-distance labels + error counts")
         out["hard_decision"] = bench_hard(const, w, ys, tx_t, max(2, min(args.steps, 5)))

@@ -268,13 +268,22 @@ int dm_mlp_load(const dm_constellation* c, const char* path, dm_mlp** out);
  *   y           HOST array of n_blk DEVICE pointers, each N x D FP32.
  *   tx          DEVICE, N uint16 transmitted ROW indices; required when counting, else may be NULL.
  *   labels_out  HOST array of n_blk DEVICE pointers (N uint16 decided LABELS each) or NULL.
- *   sym_err, bit_err  HOST int64 n_blk outputs, or NULL (no counting, no synchronisation).
- * Distances are FP32: t_d = y_d - x_d, acc = fma(t_d, t_d, acc) for d = 0..D-1 from acc = 0;
- * ties go to the lowest label.  Bit errors are the popcount of (decided label XOR sent label).
- * Synchronises `stream` when counting.  Errors: DM_EINVAL, DM_EHIP, DM_ENOMEM.
+ *   sym_err, bit_err  HOST int64 n_blk outputs, or NULL (no counting).
+ *   method      DM_HARD_AUTO, DM_HARD_VALU or DM_HARD_MFMA (see below); all give the same decisions.
+ *   n_exact     HOST int64 or NULL: symbols the MFMA method passed to the exact path.
+ * The decision is defined by FP32 distances t_d = y_d - x_d, acc = fma(t_d, t_d, acc) for
+ * d = 0..D-1 from acc = 0, ties to the lowest label.  DM_HARD_VALU evaluates exactly that for
+ * every point.  DM_HARD_MFMA (M >= 32, D <= 8, point norms^2 < 60000) ranks the points with a
+ * split-FP16 MFMA cross term and accepts its winner only when the gap to the runner-up exceeds
+ * twice a bound on the error of both computations; other symbols are decided by the FP32
+ * formula.  DM_HARD_AUTO picks DM_HARD_MFMA when it applies.  Bit errors are the popcount of
+ * (decided label XOR sent label).  Synchronises `stream` when counting or when n_exact is given.
+ * Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_EHIP, DM_ENOMEM.
  */
+enum { DM_HARD_AUTO = 0, DM_HARD_VALU = 1, DM_HARD_MFMA = 2 };
 int dm_hard_decision(const dm_constellation* c, int n_blk, const float* const* y, const uint16_t* tx, int64_t N,
-                     uint16_t* const* labels_out, int64_t* sym_err, int64_t* bit_err, void* stream);
+                     uint16_t* const* labels_out, int64_t* sym_err, int64_t* bit_err, int32_t method,
+                     int64_t* n_exact, void* stream);
 
 /* Q-factor in dB from a bit-error ratio, 20 log10(sqrt(2) erfcinv(2 BER)) (the usual Gaussian
  * reading; the paper quotes Q-factors without a formula).  NaN unless 0 < ber < 0.5. */

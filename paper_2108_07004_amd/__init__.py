@@ -98,7 +98,7 @@ def load_library():
     lib.dm_mlp_save.restype = I
     lib.dm_mlp_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(P)]
     lib.dm_mlp_load.restype = I
-    lib.dm_hard_decision.argtypes = [P, I, P, P, I64, P, P, P, P]
+    lib.dm_hard_decision.argtypes = [P, I, P, P, I64, P, P, P, ctypes.c_int32, P, P]
     lib.dm_hard_decision.restype = I
     lib.dm_q_factor_db.argtypes = [D]
     lib.dm_q_factor_db.restype = D
@@ -500,12 +500,18 @@ def demap_learned(net: MLP, const: Constellation, sigma2: Sequence[float], ys, t
     return gmi, loss, fb
 
 
-def hard_decision(const: Constellation, ys, tx=None, labels=None, count: bool = True, stream=None):
+HARD_METHOD = {"auto": 0, "valu": 1, "mfma": 2}
+
+
+def hard_decision(const: Constellation, ys, tx=None, labels=None, count: bool = True, method: str = "auto",
+                  return_exact: bool = False, stream=None):
     """Minimum-distance decisions of n_blk received blocks (dm_hard_decision).
 
     ys: list of (N, D) FP32 tensors; tx: (N,) int16/uint16 rows (needed for counting);
-    labels: None or a list of (N,) int16/uint16 tensors receiving the decided labels.
-    Returns (symbol_errors, bit_errors) int64 NumPy arrays, or (None, None) without counting.
+    labels: None or a list of (N,) int16/uint16 tensors receiving the decided labels;
+    method: "auto", "valu" or "mfma" (same decisions).
+    Returns (symbol_errors, bit_errors) int64 NumPy arrays, or (None, None) without counting;
+    with return_exact, also the number of symbols the MFMA method sent to the exact path.
     """
     nb = len(ys)
     N = int(ys[0].shape[0])
@@ -516,12 +522,14 @@ def hard_decision(const: Constellation, ys, tx=None, labels=None, count: bool = 
         lptr = (ctypes.c_void_p * nb)(*[_dev_tensor(t, ("int16", "uint16"), (N,), "labels[s]").value for t in labels])
     se = np.zeros(nb, dtype=np.int64) if count else None
     be = np.zeros(nb, dtype=np.int64) if count else None
+    nx = ctypes.c_int64(0)
     _check(load_library().dm_hard_decision(
         const.handle, nb, ctypes.cast(yptr, ctypes.c_void_p), txp, N,
         None if lptr is None else ctypes.cast(lptr, ctypes.c_void_p),
         None if se is None else se.ctypes.data_as(ctypes.c_void_p),
-        None if be is None else be.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)))
-    return se, be
+        None if be is None else be.ctypes.data_as(ctypes.c_void_p), HARD_METHOD[method],
+        ctypes.byref(nx) if return_exact else None, _stream_handle(stream)))
+    return (se, be, int(nx.value)) if return_exact else (se, be)
 
 
 def q_factor_db(ber: float) -> float:

@@ -15,13 +15,16 @@ using dmapi::fail;
 extern "C" {
 
 int dm_hard_decision(const dm_constellation* cc, int n_blk, const float* const* y, const uint16_t* tx, int64_t N,
-                     uint16_t* const* labels_out, int64_t* sym_err, int64_t* bit_err, void* stream) {
+                     uint16_t* const* labels_out, int64_t* sym_err, int64_t* bit_err, int32_t method,
+                     int64_t* n_exact, void* stream) {
     dmapi::clear_error();
     auto* c = const_cast<dm_constellation*>(cc);
     if (!c || !y) return fail(DM_EINVAL, "null argument");
     if (n_blk < 1) return fail(DM_EINVAL, "n_blk=%d < 1", n_blk);
     if (N < 0 || N >= (int64_t(1) << 31)) return fail(DM_EINVAL, "N=%lld out of range", (long long)N);
+    if (method < DM_HARD_AUTO || method > DM_HARD_MFMA) return fail(DM_EINVAL, "unknown method %d", method);
     const bool counting = sym_err || bit_err;
+    if (n_exact) *n_exact = 0;
     if (N == 0) {  // no symbols: nothing to read (empty device buffers may be null)
         for (int s = 0; s < n_blk; ++s) {
             if (sym_err) sym_err[s] = 0;
@@ -29,6 +32,10 @@ int dm_hard_decision(const dm_constellation* cc, int n_blk, const float* const* 
         }
         return DM_OK;
     }
+    const bool mfma_ok = c->M >= 32 && c->D <= 8 && c->max_norm < 60000.0f;
+    if (method == DM_HARD_MFMA && !mfma_ok)
+        return fail(DM_EUNSUPPORTED, "MFMA decisions need M >= 32, D <= 8 and point norms inside the FP16 range");
+    const bool use_mfma = method == DM_HARD_MFMA || (method == DM_HARD_AUTO && mfma_ok);
     if (counting && !tx) return fail(DM_EINVAL, "error counts need the transmitted rows (tx)");
     int r;
     if ((r = dmapi::check_current_device(c))) return r;
@@ -38,9 +45,11 @@ int dm_hard_decision(const dm_constellation* cc, int n_blk, const float* const* 
         if (labels_out && (r = dmapi::check_device_ptr(labels_out[s], "labels_out[s]", c->device))) return r;
     }
     std::lock_guard<std::mutex> lock(c->mu);
-    if ((r = dmapi::ensure_scratch(c, 0))) return r;
+    if ((r = dmapi::ensure_scratch(c, use_mfma ? (uint64_t)N * std::min(n_blk, dm::kMaxSnrPerLaunch) : 0))) return r;
+    if (use_mfma && (r = dmapi::ensure_frag(c, DM_PREC_FP16X3, false))) return r;
     hipStream_t st = (hipStream_t)stream;
-    const int tile = dm::hard_tile_symbols();
+    const int tile = use_mfma ? dm::hard_mfma_block_symbols() : dm::hard_tile_symbols();
+    int64_t exact_total = 0;
     for (int s0 = 0; s0 < n_blk; s0 += dm::kMaxSnrPerLaunch) {
         const int nb = std::min(dm::kMaxSnrPerLaunch, n_blk - s0);
         dm::HardArgs a;
@@ -64,8 +73,22 @@ int dm_hard_decision(const dm_constellation* cc, int n_blk, const float* const* 
             DM_HIP_TRY(hipMemsetAsync(a.bad_tx, 0, sizeof(uint32_t), st));
         }
         const int64_t work = a.tiles_per_blk * nb;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)c->cus * 2));
-        DM_HIP_TRY(dm::launch_hard_demap(a, grid, st));
+        if (use_mfma) {
+            DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)c->cus));
+            DM_HIP_TRY(dm::launch_hard_mfma(a, c->d_frag[DM_PREC_FP16X3], std::sqrt(c->max_norm), c->d_queue,
+                                            c->d_queue_count, c->queue_cap, grid, st));
+            DM_HIP_TRY(dm::launch_hard_fix(a, c->d_queue, c->d_queue_count, c->queue_cap, c->cus * 4, st));
+        } else {
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)c->cus * 2));
+            DM_HIP_TRY(dm::launch_hard_demap(a, grid, st));
+        }
+        if (use_mfma && n_exact) {
+            uint32_t q = 0;
+            DM_HIP_TRY(hipMemcpyAsync(&q, c->d_queue_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            DM_HIP_TRY(hipStreamSynchronize(st));
+            exact_total += q;
+        }
         if (counting) {
             auto* h = (unsigned long long*)c->h_stage;
             auto* bad = (uint32_t*)(h + 2 * dm::kMaxSnrPerLaunch);
@@ -79,6 +102,7 @@ int dm_hard_decision(const dm_constellation* cc, int n_blk, const float* const* 
             }
         }
     }
+    if (n_exact) *n_exact = exact_total;
     return DM_OK;
 }
 

@@ -1,0 +1,318 @@
+// Minimum-distance decisions with the distance cross term on MFMA (gfx950), exact by proof.
+//
+// The split-FP16 MFMA (three products per term, FP32 accumulation) yields for every symbol and
+// point u~ = K + 2 y.x - ||x||^2 - ||y||^2 = K - ||y - x||^2, with a per-symbol offset
+// K = (||y|| + r_max)^2 + 1 that keeps every u~ positive, so the bit patterns of the u~ order
+// like their values.  Register r of tile t holds label 32 t + 16 h + r; each lane keeps, per
+// register slot r, the largest value with the (complemented) tile index written into its low
+// 7 mantissa bits, and one running maximum of everything that lost a comparison (the overall
+// runner-up once combined with the slots): four vector instructions per (symbol, point), all
+// unsigned integer max / min.  Per value, |u~ - u| is at most 3.5e-6 K (FP32 accumulation of
+// 3D + 5 terms bounded by 2K) + 1e-6 K (operand splitting, dropped lo*lo products) + 5.4e-7 K
+// (rounding of the reference FP32 distance) + 7.6e-6 K (the 7 packed bits), under 1.3e-5 K in
+// all; with eps = 2^-14 K (+ a floor for FP16 subnormal lo parts) a gap best - second > 2 eps
+// proves the winner is the unique minimiser of the reference FP32 distance, so it is the
+// decision.  Otherwise (near or exact ties, values out of FP16 range, non-finite inputs) the
+// symbol is queued and hard_fix_kernel decides it with the reference formula itself (lowest
+// label among equal distances).
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "mfma_body.hpp"
+
+namespace dm {
+
+namespace {
+
+constexpr int kHardMfmaThreads = 1024;
+constexpr int kHardMfmaLds = 131072;
+constexpr uint32_t kTileMask = 0x7Fu;  // packed tile index: M <= 4096 (t < 128)
+
+// Reference FP32 distance of the library's hard decisions.
+template <int DP>
+__device__ __forceinline__ float ref_dist(const float (&y)[DP], const float* x) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int d = 0; d < DP; ++d) {
+        const float t = y[d] - x[d];
+        acc = __builtin_fmaf(t, t, acc);
+    }
+    return acc;
+}
+
+// Exact decision of one symbol by one lane (queue overflow path).
+template <int DP>
+__device__ int lane_exact(const float (&y)[DP], const float* table, int M) {
+    float best = __builtin_inff();
+    int arg = 0;
+    for (int j = 0; j < M; ++j) {
+        const float d = ref_dist<DP>(y, table + (size_t)j * DP);
+        if (d < best) {
+            best = d;
+            arg = j;
+        }
+    }
+    return arg;
+}
+
+template <int D>
+__global__ __launch_bounds__(kHardMfmaThreads) void hard_mfma_kernel(const HardArgs a, const uint4* __restrict__ frag,
+                                                                     float r_max, FixEntry* queue,
+                                                                     uint32_t* queue_count, uint32_t queue_cap) {
+    using T = _Float16;
+    constexpr int S = Slots<D, true>::S;
+    using V = typename Mma<T>::V;
+    extern __shared__ uint4 lds_frag[];
+    const int ntiles = a.M >> 5;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int h = lane >> 5;
+    const int wave = tid >> 6;
+    constexpr int kWaves = kHardMfmaThreads / 64;
+    const int chunk_tiles = min(ntiles, kHardMfmaLds / (S * 64 * 16));
+    const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
+    auto stage = [&](int t0, int cnt) {
+        const uint4* src = frag + (size_t)t0 * S * 64;
+        for (int i = tid; i < cnt * S * 64; i += kHardMfmaThreads) lds_frag[i] = src[i];
+    };
+    if (nchunks == 1) {
+        stage(0, ntiles);
+        __syncthreads();
+    }
+    const int64_t sym_per_blk = (int64_t)kWaves * 32;
+    const int64_t blks = (a.N + sym_per_blk - 1) / sym_per_blk;
+    const int64_t total = blks * a.n_blk;
+    uint32_t se = 0, be = 0;
+    int cur = -1;
+    auto flush = [&]() {
+        if (cur < 0 || !a.counts) return;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            se += __shfl_xor(se, off, 64);
+            be += __shfl_xor(be, off, 64);
+        }
+        if (lane == 0) {
+            if (se) atomicAdd(a.counts + 2 * cur, (unsigned long long)se);
+            if (be) atomicAdd(a.counts + 2 * cur + 1, (unsigned long long)be);
+        }
+        se = be = 0;
+    };
+    for (int64_t bt = blockIdx.x; bt < total; bt += gridDim.x) {
+        const int s = (int)(bt / blks);
+        const int64_t n = (bt % blks) * sym_per_blk + wave * 32 + (lane & 31);
+        if (s != cur) {
+            flush();
+            cur = s;
+        }
+        const bool active = n < a.N;
+        float y[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) y[d] = active ? a.y[s][(size_t)n * D + d] : 0.0f;
+        float ysq = 0.0f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ysq = fmaf(y[d], y[d], ysq);
+        const float rr = sqrtf(ysq) + r_max;
+        const float K = fmaf(rr, rr, 1.0f);
+        bool bad = false;
+        const Frags<T, S> bfr = build_symbol_frags<T, D, true>(y, 1.0f, K, h, bad);
+        // per register slot r: largest packed u~ (field = kTileMask - t); sec: largest loser
+        uint32_t best[16], sec = 0u;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) best[r] = 0u;
+        // the mask lives in a register so that masking and inserting the (scalar) tile field is
+        // one v_and_or_b32 (a literal mask and a scalar field would need two instructions)
+        uint32_t keep = ~kTileMask;
+        asm volatile("" : "+v"(keep));
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int t0 = ch * chunk_tiles;
+            const int cnt = min(chunk_tiles, ntiles - t0);
+            if (nchunks > 1) {
+                __syncthreads();
+                stage(t0, cnt);
+                __syncthreads();
+            }
+            auto tile_mma = [&](int t) {
+                const uint4* fp = lds_frag + (size_t)t * S * 64 + lane;
+                f32x16 acc = Mma<T>::run(__builtin_bit_cast(V, fp[0]), bfr.v[0]);
+#pragma unroll
+                for (int q = 1; q < S; ++q) acc = Mma<T>::run(__builtin_bit_cast(V, fp[q * 64]), bfr.v[q], acc);
+                return acc;
+            };
+            auto consume = [&](const f32x16& acc, int t) {
+                const uint32_t field = kTileMask - (uint32_t)(t0 + t);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t e = (__float_as_uint(acc[r]) & keep) | field;
+                    sec = max(sec, min(best[r], e));
+                    best[r] = max(best[r], e);
+                }
+            };
+            // the MFMAs of tile t+1 are issued before tile t is consumed (alternating accumulators)
+            const int last = cnt - 1;
+            f32x16 acc0 = tile_mma(0), acc1;
+            for (int t = 0; t < cnt; t += 2) {
+                acc1 = tile_mma(min(t + 1, last));
+                consume(acc0, t);
+                if (t + 1 < cnt) {
+                    acc0 = tile_mma(min(t + 2, last));
+                    consume(acc1, t + 1);
+                }
+            }
+        }
+        // this half's winner (slot r1) and runner-up, then the two halves of the symbol
+        uint32_t b1 = best[0], b2 = 0u;
+        int r1 = 0;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) {
+            b2 = max(b2, min(b1, best[r]));
+            r1 = best[r] > b1 ? r : r1;
+            b1 = max(b1, best[r]);
+        }
+        const uint32_t s1 = max(sec, b2);
+        const uint32_t pb = __shfl_xor(b1, 32, 64), ps = __shfl_xor(s1, 32, 64);
+        const int pr = __shfl_xor(r1, 32, 64);
+        const bool pbad = __shfl_xor((int)bad, 32, 64);
+        const uint32_t bg = max(b1, pb);
+        const uint32_t sg = max(max(s1, ps), min(b1, pb));
+        const bool mine = b1 >= pb;
+        const int tw = (int)(kTileMask - (bg & kTileMask));
+        const int label = 32 * tw + 16 * (mine ? h : 1 - h) + (mine ? r1 : pr);
+        const float gap = __uint_as_float(bg & ~kTileMask) - __uint_as_float(sg & ~kTileMask);
+        const float eps = 0x1p-14f * K + 0x1p-18f * (1.0f + rr);
+        const bool ok = !bad && !pbad && (gap > 2.0f * eps) && (gap < __builtin_inff()) && label < a.M;
+        if (h == 0 && active) {
+            int dec = label;
+            bool decided = ok;
+            if (!ok) {
+                const uint32_t slot = atomicAdd(queue_count, 1u);
+                if (slot < queue_cap) {
+                    queue[slot] = FixEntry{(uint32_t)n, (uint32_t)s, 0u, 0u};
+                } else {
+                    float yp[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) yp[d] = y[d];
+                    dec = lane_exact<D>(yp, a.table, a.M);
+                    decided = true;
+                }
+            }
+            if (decided) {
+                if (a.labels_out[s]) a.labels_out[s][n] = (uint16_t)dec;
+                if (a.counts) {
+                    uint32_t row = a.tx[n];
+                    if (row >= (uint32_t)a.M) {
+                        atomicOr(a.bad_tx, 1u);
+                        row = 0;
+                    }
+                    const uint32_t txl = a.row2label[row];
+                    se += (uint32_t)dec != txl;
+                    be += __builtin_popcount((uint32_t)dec ^ txl);
+                }
+            }
+        }
+    }
+    flush();
+}
+
+// One wavefront per queued symbol: the reference FP32 distance to every point, lanes striding
+// over the label-ordered table, then the smallest distance and among equal ones the lowest label.
+template <int DP>
+__global__ __launch_bounds__(256) void hard_fix_kernel(const HardArgs a, const FixEntry* queue, const uint32_t* count_p,
+                                                       uint32_t cap) {
+    const uint32_t count = min(*count_p, cap);
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwaves = gridDim.x * 4;
+    for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < count; i += nwaves) {
+        const FixEntry e = queue[i];
+        const int s = (int)e.tag;
+        const int64_t n = e.n;
+        float y[DP];
+        load_symbol<DP>(y, a.y[s] + (size_t)n * a.D, a.D, true);
+        float best = __builtin_inff();
+        int arg = a.M;  // none yet
+        for (int j = lane; j < a.M; j += 64) {
+            const float d = ref_dist<DP>(y, a.table + (size_t)j * DP);
+            if (d < best) {
+                best = d;
+                arg = j;
+            }
+        }
+        float bmin = best;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) bmin = fminf(bmin, __shfl_xor(bmin, off, 64));
+        int cand = (best == bmin) ? arg : a.M;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
+        if (cand >= a.M) cand = 0;  // every distance NaN: the lowest label
+        if (lane == 0) {
+            if (a.labels_out[s]) a.labels_out[s][n] = (uint16_t)cand;
+            if (a.counts) {
+                uint32_t row = a.tx[n];
+                if (row >= (uint32_t)a.M) {
+                    atomicOr(a.bad_tx, 1u);
+                    row = 0;
+                }
+                const uint32_t txl = a.row2label[row];
+                if ((uint32_t)cand != txl) atomicAdd(a.counts + 2 * s, 1ull);
+                const uint32_t nb = __builtin_popcount((uint32_t)cand ^ txl);
+                if (nb) atomicAdd(a.counts + 2 * s + 1, (unsigned long long)nb);
+            }
+        }
+    }
+}
+
+template <int D>
+hipError_t launch_hard_mfma_t(const HardArgs& a, const void* frag, float r_max, FixEntry* queue, uint32_t* qcount,
+                              uint32_t qcap, int grid, hipStream_t st) {
+    constexpr int S = Slots<D, true>::S;
+    const int ntiles = a.M >> 5;
+    const int chunk_tiles = std::min(ntiles, kHardMfmaLds / (S * 64 * 16));
+    const size_t lds = (size_t)chunk_tiles * S * 64 * 16;
+    auto kern = hard_mfma_kernel<D>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kHardMfmaThreads), lds, st, a, (const uint4*)frag, r_max, queue, qcount,
+                       qcap);
+    return hipGetLastError();
+}
+
+template <int DP>
+hipError_t launch_hard_fix_t(const HardArgs& a, const FixEntry* queue, const uint32_t* qcount, uint32_t qcap, int grid,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(hard_fix_kernel<DP>, dim3(grid), dim3(256), 0, st, a, queue, qcount, qcap);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int hard_mfma_block_symbols() { return (kHardMfmaThreads / 64) * 32; }
+
+hipError_t launch_hard_mfma(const HardArgs& a, const void* frag, float r_max, FixEntry* queue, uint32_t* qcount,
+                            uint32_t qcap, int grid, hipStream_t st) {
+    switch (a.D) {
+        case 1: return launch_hard_mfma_t<1>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 2: return launch_hard_mfma_t<2>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 3: return launch_hard_mfma_t<3>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 4: return launch_hard_mfma_t<4>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 5: return launch_hard_mfma_t<5>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 6: return launch_hard_mfma_t<6>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 7: return launch_hard_mfma_t<7>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        case 8: return launch_hard_mfma_t<8>(a, frag, r_max, queue, qcount, qcap, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_hard_fix(const HardArgs& a, const FixEntry* queue, const uint32_t* qcount, uint32_t qcap, int grid,
+                           hipStream_t st) {
+    switch (a.D) {
+        case 1: return launch_hard_fix_t<1>(a, queue, qcount, qcap, grid, st);
+        case 2: return launch_hard_fix_t<2>(a, queue, qcount, qcap, grid, st);
+        case 3: return launch_hard_fix_t<3>(a, queue, qcount, qcap, grid, st);
+        case 4: return launch_hard_fix_t<4>(a, queue, qcount, qcap, grid, st);
+        case 5: return launch_hard_fix_t<5>(a, queue, qcount, qcap, grid, st);
+        case 6: return launch_hard_fix_t<6>(a, queue, qcount, qcap, grid, st);
+        case 7: return launch_hard_fix_t<7>(a, queue, qcount, qcap, grid, st);
+        case 8: return launch_hard_fix_t<8>(a, queue, qcount, qcap, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dm

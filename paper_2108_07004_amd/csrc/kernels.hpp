@@ -13,6 +13,13 @@ int padded_dim(int D);
 int valu_tile_symbols();
 int hard_tile_symbols();
 hipError_t launch_hard_demap(const HardArgs& a, int grid, hipStream_t st);
+int hard_mfma_block_symbols();
+// MFMA decisions (split-FP16 operand table `frag` of the label-order points, r_max = max ||x||);
+// ambiguous symbols go to `queue` (FixEntry n = symbol, tag = block) for launch_hard_fix.
+hipError_t launch_hard_mfma(const HardArgs& a, const void* frag, float r_max, FixEntry* queue, uint32_t* qcount,
+                            uint32_t qcap, int grid, hipStream_t st);
+hipError_t launch_hard_fix(const HardArgs& a, const FixEntry* queue, const uint32_t* qcount, uint32_t qcap, int grid,
+                           hipStream_t st);
 
 // FP32 direct-difference demapper (one lane per symbol, persistent grid).
 hipError_t launch_demap_valu(const LaunchArgs& a, int grid, hipStream_t st);

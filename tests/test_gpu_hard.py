@@ -36,13 +36,19 @@ def _check(const_np, N, snrs, config, extra=()):
     z = W.unit_noise(N, D, config, *extra)
     s2 = W.sigma2_from_snr_db(np.asarray(snrs, dtype=np.float64))
     ys = [W.awgn(const_np.points, tx, z, v) for v in s2]
-    outs = [_labels_like(N) for _ in s2]
-    se, be = dm.hard_decision(c, [_dev(y) for y in ys], _dev(tx.view(np.int16)), outs)
-    for i, y in enumerate(ys):
-        ref = oracle.hard_demap(const_np.points, const_np.labels, y, tx)
-        got = outs[i].cpu().numpy().view(np.uint16)
-        assert np.array_equal(got, ref["labels"]), (i, int(np.sum(got != ref["labels"])))
-        assert se[i] == ref["sym_err"] and be[i] == ref["bit_err"], (i, se[i], be[i], ref)
+    refs = [oracle.hard_demap(const_np.points, const_np.labels, y, tx) for y in ys]
+    methods = ["valu", "mfma"] if (M >= 32 and D <= 8) else ["valu"]
+    for method in methods:
+        outs = [_labels_like(N) for _ in s2]
+        se, be, nx = dm.hard_decision(c, [_dev(y) for y in ys], _dev(tx.view(np.int16)), outs, method=method,
+                                      return_exact=True)
+        if method == "valu":
+            assert nx == 0
+        for i, ref in enumerate(refs):
+            got = outs[i].cpu().numpy().view(np.uint16)
+            assert np.array_equal(got, ref["labels"]), (method, i, int(np.sum(got != ref["labels"])))
+            assert se[i] == ref["sym_err"] and be[i] == ref["bit_err"], (method, i, se[i], be[i], ref)
+        print(f"M={M} D={D} {method}: {nx} of {N * len(s2)} symbols decided by the exact path")
 
 
 def test_dpqpsk():
@@ -60,6 +66,27 @@ def test_gauss8d2048_prefix():
 def test_padded_dimension_and_chunked_table():
     _check(W.gaussian_constellation(64, 12, 60), 3001, [3, 12], 60, (1,))
     _check(W.gaussian_constellation(4096, 8, 61), 1500, [8], 61, (1,))
+
+
+def test_mfma_method_routes_ties_to_the_exact_path():
+    # 64-QAM with received points exactly on decision boundaries (midpoints between neighbours)
+    c = W.qam(64)
+    const = dm.Constellation(c.points, c.labels)
+    g = W.rng(62, "misc", 0)
+    i = g.integers(0, 64, 4096)
+    j = g.integers(0, 64, 4096)
+    y = (0.5 * (c.points[i].astype(np.float64) + c.points[j].astype(np.float64))).astype(np.float32)
+    y[:16] = np.nan
+    out = _labels_like(4096)
+    tx = _dev(i.astype(np.uint16).view(np.int16))
+    se, be, nx = dm.hard_decision(const, [_dev(y)], tx, [out], method="mfma", return_exact=True)
+    ref = oracle.hard_demap(c.points, c.labels, y, i.astype(np.uint16))
+    assert np.array_equal(out.cpu().numpy().view(np.uint16), ref["labels"])
+    assert se[0] == ref["sym_err"] and be[0] == ref["bit_err"]
+    assert nx >= int(np.sum(i != j)) // 2  # exact ties cannot be decided by the MFMA ranking
+    with pytest.raises(dm.DemapError):
+        dm.hard_decision(dm.Constellation(W.dp_qpsk().points, W.dp_qpsk().labels),
+                         [_dev(np.zeros((4, 4), np.float32))], None, None, count=False, method="mfma")
 
 
 def test_ties_nan_and_empty():
