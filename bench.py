@@ -209,6 +209,28 @@ def bench_hard(const, w, ys, tx_t, steps):
             "q_db": [None if not (0 < b < 0.5) else round(dm.q_factor_db(float(b)), 3) for b in ber]}
 
 
+def bench_stream(const, w, ys, prec, buffer_symbols=1 << 20, n_buffers=3):
+    """Host-to-host streamed demapping of one received block (PCIe transfers included)."""
+    import torch
+
+    import paper_2108_07004_amd as dm
+
+    y = torch.empty((w.N, w.const.D), dtype=torch.float32, pin_memory=True)
+    y.copy_(ys[len(ys) // 2])
+    llr = torch.empty((w.N, w.const.m), dtype=torch.float32, pin_memory=True)
+    s2 = float(w.sigma2[len(ys) // 2])
+    st = dm.Streamer(const, buffer_symbols=buffer_symbols, n_buffers=n_buffers, prec=prec)
+    st.run(s2, y[: 4 * buffer_symbols], llr[: 4 * buffer_symbols])  # warm-up
+    _, sec = st.run(s2, y, llr)
+    st.close()
+    del y, llr
+    per_sym = 4 * (w.const.D + w.const.m)
+    return {"workload": f"{w.name}: one block of N={w.N} from pinned host memory, LLRs back to pinned host memory, "
+                        f"{buffer_symbols}-symbol buffers, {n_buffers} slots, {prec}",
+            "symbols_per_s": w.N / sec, "seconds": sec, "pcie_bytes_per_symbol": per_sym,
+            "pcie_GB_per_s": w.N * per_sym / sec / 1e9}
+
+
 def bench_gs(iters=100, candidates=32, N=1 << 16):
     """GMI-driven shaping search from rectangular 8-QAM at 14 dB (the paper's GS-8 design point)."""
     import torch
