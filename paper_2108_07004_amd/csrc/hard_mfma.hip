@@ -212,50 +212,74 @@ __global__ __launch_bounds__(kHardMfmaThreads) void hard_mfma_kernel(const HardA
     flush();
 }
 
-// One wavefront per queued symbol: the reference FP32 distance to every point, lanes striding
-// over the label-ordered table, then the smallest distance and among equal ones the lowest label.
+// One lane per queued symbol: the reference FP32 distance to every point of the label-ordered
+// table, staged in LDS and read with wave-uniform addresses (broadcast), strict "<" in label
+// order (ties to the lowest label).  All threads of a block run the same number of rounds so
+// the chunked staging can synchronise the block.
+constexpr int kFixThreads = 256;
+constexpr int kFixLdsFloats = 16384;  // 64 KiB of points per staged chunk
+
 template <int DP>
-__global__ __launch_bounds__(256) void hard_fix_kernel(const HardArgs a, const FixEntry* queue, const uint32_t* count_p,
-                                                       uint32_t cap) {
+__global__ __launch_bounds__(kFixThreads) void hard_fix_kernel(const HardArgs a, const FixEntry* queue,
+                                                                const uint32_t* count_p, uint32_t cap) {
+    extern __shared__ float lds[];
+    __shared__ unsigned long long s_cnt[2 * kMaxSnrPerLaunch];  // per block: symbol, bit errors
     const uint32_t count = min(*count_p, cap);
-    const int lane = threadIdx.x & 63;
-    const uint32_t nwaves = gridDim.x * 4;
-    for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < count; i += nwaves) {
-        const FixEntry e = queue[i];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 2 * kMaxSnrPerLaunch; q += kFixThreads) s_cnt[q] = 0ull;
+    int chunk = (kFixLdsFloats / DP) & ~63;
+    if (chunk >= a.M) chunk = a.M;
+    const int nchunks = (a.M + chunk - 1) / chunk;
+    if (nchunks == 1)
+        for (int i = tid; i < a.M * DP; i += kFixThreads) lds[i] = a.table[i];
+    __syncthreads();
+    const uint32_t stride = gridDim.x * kFixThreads;
+    const uint32_t rounds = (count + stride - 1) / stride;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t i = rd * stride + blockIdx.x * kFixThreads + tid;
+        const bool live = i < count;
+        FixEntry e{0u, 0u, 0u, 0u};
+        if (live) e = queue[i];
         const int s = (int)e.tag;
-        const int64_t n = e.n;
         float y[DP];
-        load_symbol<DP>(y, a.y[s] + (size_t)n * a.D, a.D, true);
+        load_symbol<DP>(y, a.y[s] + (size_t)e.n * a.D, a.D, live);
         float best = __builtin_inff();
-        int arg = a.M;  // none yet
-        for (int j = lane; j < a.M; j += 64) {
-            const float d = ref_dist<DP>(y, a.table + (size_t)j * DP);
-            if (d < best) {
-                best = d;
-                arg = j;
+        int arg = 0;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int c0 = ch * chunk;
+            const int cnt = min(chunk, a.M - c0);
+            if (nchunks > 1) {
+                __syncthreads();
+                for (int q = tid; q < cnt * DP; q += kFixThreads) lds[q] = a.table[(size_t)c0 * DP + q];
+                __syncthreads();
+            }
+#pragma unroll 8
+            for (int j = 0; j < cnt; ++j) {
+                const float d = ref_dist<DP>(y, lds + j * DP);
+                const bool better = d < best;
+                best = better ? d : best;
+                arg = better ? c0 + j : arg;
             }
         }
-        float bmin = best;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) bmin = fminf(bmin, __shfl_xor(bmin, off, 64));
-        int cand = (best == bmin) ? arg : a.M;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) cand = min(cand, __shfl_xor(cand, off, 64));
-        if (cand >= a.M) cand = 0;  // every distance NaN: the lowest label
-        if (lane == 0) {
-            if (a.labels_out[s]) a.labels_out[s][n] = (uint16_t)cand;
+        if (live) {
+            if (a.labels_out[s]) a.labels_out[s][e.n] = (uint16_t)arg;
             if (a.counts) {
-                uint32_t row = a.tx[n];
+                uint32_t row = a.tx[e.n];
                 if (row >= (uint32_t)a.M) {
                     atomicOr(a.bad_tx, 1u);
                     row = 0;
                 }
                 const uint32_t txl = a.row2label[row];
-                if ((uint32_t)cand != txl) atomicAdd(a.counts + 2 * s, 1ull);
-                const uint32_t nb = __builtin_popcount((uint32_t)cand ^ txl);
-                if (nb) atomicAdd(a.counts + 2 * s + 1, (unsigned long long)nb);
+                if ((uint32_t)arg != txl) atomicAdd(&s_cnt[2 * s], 1ull);
+                const uint32_t nb = __builtin_popcount((uint32_t)arg ^ txl);
+                if (nb) atomicAdd(&s_cnt[2 * s + 1], (unsigned long long)nb);
             }
         }
+    }
+    if (a.counts) {  // one global update per block and counter
+        __syncthreads();
+        for (int q = tid; q < 2 * a.n_blk; q += kFixThreads)
+            if (s_cnt[q]) atomicAdd(a.counts + q, s_cnt[q]);
     }
 }
 
@@ -277,7 +301,11 @@ hipError_t launch_hard_mfma_t(const HardArgs& a, const void* frag, float r_max, 
 template <int DP>
 hipError_t launch_hard_fix_t(const HardArgs& a, const FixEntry* queue, const uint32_t* qcount, uint32_t qcap, int grid,
                              hipStream_t st) {
-    hipLaunchKernelGGL(hard_fix_kernel<DP>, dim3(grid), dim3(256), 0, st, a, queue, qcount, qcap);
+    const size_t lds = sizeof(float) * (size_t)std::min(a.M * DP, kFixLdsFloats);
+    hipError_t e = hipFuncSetAttribute((const void*)hard_fix_kernel<DP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hard_fix_kernel<DP>, dim3(grid), dim3(kFixThreads), lds, st, a, queue, qcount, qcap);
     return hipGetLastError();
 }
 
