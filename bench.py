@@ -179,7 +179,7 @@ def bench_learned(const, w, ys, tx_t, llrs, exact_gmi, exact_sym_per_s, exact_pr
     }
 
 
-def bench_hard(const, w, ys, tx_t, steps):
+def bench_hard(const, w, ys, tx_t, steps, method="auto"):
     """Minimum-distance decisions of the headline block (labels written, symbol / bit errors counted).
 
     Priced per (symbol, point) pair against the vector-ALU issue rate (one lane-operation per
@@ -191,17 +191,18 @@ def bench_hard(const, w, ys, tx_t, steps):
     dev = torch.device("cuda:0")
     outs = [torch.empty(w.N, dtype=torch.int16, device=dev) for _ in ys]
     se = be = None
-    dm.hard_decision(const, ys, tx_t, outs)
+    dm.hard_decision(const, ys, tx_t, outs, method=method)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        se, be, nx = dm.hard_decision(const, ys, tx_t, outs, return_exact=True)
+        se, be, nx = dm.hard_decision(const, ys, tx_t, outs, method=method, return_exact=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     n_sym = w.N * len(ys)
     pairs = float(n_sym) * w.const.M
     ber = be / (w.N * w.const.m)
     return {"workload": f"{w.name}: N={w.N} x {len(ys)} blocks, min-distance labels + symbol/bit error counts",
+            "method": method,
             "symbols_per_s": n_sym / dt, "ms_per_step": dt * 1e3, "exact_path_symbols": nx,
             "roofline": {"bound": "alu", "achieved": pairs / dt / 1e12, "peak": FULL_RATE / 1e12,
                          "unit": "Tpairs/s", "frac": pairs / dt / FULL_RATE, "traffic": None},
@@ -231,25 +232,34 @@ def bench_stream(const, w, ys, prec, buffer_symbols=1 << 20, n_buffers=3):
             "pcie_GB_per_s": w.N * per_sym / sec / 1e9}
 
 
-def bench_gs(iters=100, candidates=32, N=1 << 16):
-    """GMI-driven shaping search from rectangular 8-QAM at 14 dB (the paper's GS-8 design point)."""
+def _gs_run(c, snr_db, iters, candidates, N, seed_key):
     import torch
 
     import paper_2108_07004_amd as dm
     import workloads as W
 
-    c = W.rect_qam(4, 2)
-    g = W.rng(70, "misc", 0)
-    tx = torch.from_numpy(g.integers(0, 8, size=N).astype(np.int16)).cuda()
+    g = W.rng(70, "misc", seed_key)
+    tx = torch.from_numpy(g.integers(0, c.M, size=N).astype(np.int16)).cuda()
     z = torch.from_numpy(g.standard_normal((N, 2)).astype(np.float32)).cuda()
-    dm.gs_optimize(c.points, c.labels, 14.0, tx, z, iters=2, candidates=candidates)  # warm-up
+    dm.gs_optimize(c.points, c.labels, snr_db, tx, z, iters=2, candidates=candidates)  # warm-up
     t0 = time.perf_counter()
-    _, _, trace, acc = dm.gs_optimize(c.points, c.labels, 14.0, tx, z, iters=iters, candidates=candidates, seed=7)
+    _, _, trace, acc = dm.gs_optimize(c.points, c.labels, snr_db, tx, z, iters=iters, candidates=candidates, seed=7)
     dt = time.perf_counter() - t0
     evals = iters * candidates
-    return {"workload": f"8-QAM at 14 dB, {iters} iterations x {candidates} candidates, N={N} common block",
+    return {"workload": f"{c.name} at {snr_db:g} dB, {iters} iterations x {candidates} candidates, "
+                        f"N={N} common block",
             "seconds": dt, "candidate_evals_per_s": evals / dt, "symbols_per_s": evals * N / dt,
             "gmi_start": round(float(trace[0]), 5), "gmi_end": round(float(trace[-1]), 5), "accepted": acc}
+
+
+def bench_gs(iters=100, candidates=32, N=1 << 16):
+    """GMI-driven shaping search from rectangular 8-QAM at 14 dB and from cross 128-QAM at 20 dB
+    (the paper's GS-8 and GS-128 design points)."""
+    import workloads as W
+
+    out = _gs_run(W.rect_qam(4, 2, "8-QAM"), 14.0, iters, candidates, N, 0)
+    out["gs128"] = _gs_run(W.cross_qam(128, "cross 128-QAM"), 20.0, iters, candidates, N, 1)
+    return out
 
 
 def main():
@@ -264,6 +274,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip training + timing the learned demapper")
     ap.add_argument("--no-hard", action="store_true", help="skip the hard-decision measurement")
+    ap.add_argument("--hard-method", default="auto", choices=["auto", "valu", "mfma"],
+                    help="hard-decision method (auto: MFMA ranking where it applies)")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-to-host streamed measurement")
     ap.add_argument("--no-gs", action="store_true", help="skip the shaping-search measurement")
     ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
@@ -371,11 +383,13 @@ def main():
     if not args.no_gs:
         log("shaping search: 8-QAM at 14 dB")
         out["gs_search"] = bench_gs()
-        log(f"shaping search: {out['gs_search']['candidate_evals_per_s']:.0f} candidates/s, GMI "
-            f"{out['gs_search']['gmi_start']} -> {out['gs_search']['gmi_end']}")
+        g8, g128 = out["gs_search"], out["gs_search"]["gs128"]
+        log(f"shaping search: 8-QAM {g8['candidate_evals_per_s']:.0f} candidates/s, GMI {g8['gmi_start']} -> "
+            f"{g8['gmi_end']}; 128-QAM {g128['candidate_evals_per_s']:.0f} candidates/s, GMI "
+            f"{g128['gmi_start']} -> {g128['gmi_end']}")
     if not args.no_hard:
         log("hard decisions: minimum-distance labels + error counts")
-        out["hard_decision"] = bench_hard(const, w, ys, tx_t, max(2, min(args.steps, 5)))
+        out["hard_decision"] = bench_hard(const, w, ys, tx_t, max(2, min(args.steps, 5)), args.hard_method)
         log(f"hard decisions: {out['hard_decision']['symbols_per_s'] / 1e9:.3f} Gsym/s")
     if not args.no_learned and w.name == "gauss8d2048":
         log("learned: training on the GPU, then learned vs exact demapping")

@@ -2,8 +2,9 @@
 
 * The GMI trace never decreases and the reported final GMI is the FP64 oracle's GMI of the
   returned constellation on the same block (1e-4 bit).
-* Starting from rectangular 8-QAM at 14 dB (the paper's GS-8 design point), the result has a
-  higher GMI than the start on an independent block (paired, common random numbers).
+* Starting from rectangular 8-QAM at 14 dB (the paper's GS-8 design point) and from cross
+  128-QAM at 20 dB (its GS-128 point), the result has a higher GMI than the start on an
+  independent block (paired, common random numbers).
 * Swaps alone keep the point set and only relabel it; a zero-iteration run returns the start.
 """
 from __future__ import annotations
@@ -62,6 +63,23 @@ def test_gs8_at_14db_improves_and_matches_oracle():
     g_new = _oracle_gmi(pts, 14.0, tx2, z2)
     g_old = _oracle_gmi(_label_order(c), 14.0, tx2, z2)
     print(f"GS-8 @14 dB: start {g_old:.5f} -> {g_new:.5f} bit on an independent block "
+          f"(search block {trace[0]:.5f} -> {trace[-1]:.5f}, {acc} accepted)")
+    assert g_new > g_old, (g_old, g_new)
+
+
+def test_gs128_at_20db_improves_and_matches_oracle():
+    c = W.cross_qam(128)
+    N = 1 << 16
+    tx, z = _block(128, 2, N, 3)
+    pts, lab, trace, acc = dm.gs_optimize(c.points, c.labels, 20.0, _dev(tx.view(np.int16)), _dev(z),
+                                          iters=80, candidates=32, perturb_sd=0.02, swap_prob=0.5, seed=11)
+    assert np.all(np.diff(trace) >= 0.0) and acc >= 1
+    assert abs(np.mean(np.sum(pts.astype(np.float64) ** 2, axis=1)) - 1.0) < 1e-6
+    assert abs(trace[-1] - _oracle_gmi(pts, 20.0, tx, z)) <= 1e-4
+    tx2, z2 = _block(128, 2, 1 << 17, 4)
+    g_new = _oracle_gmi(pts, 20.0, tx2, z2)
+    g_old = _oracle_gmi(_label_order(c), 20.0, tx2, z2)
+    print(f"GS-128 @20 dB: start {g_old:.5f} -> {g_new:.5f} bit on an independent block "
           f"(search block {trace[0]:.5f} -> {trace[-1]:.5f}, {acc} accepted)")
     assert g_new > g_old, (g_old, g_new)
 
