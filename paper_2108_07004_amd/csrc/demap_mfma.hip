@@ -41,16 +41,24 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
     const int64_t sym_per_blk = (int64_t)kWaves * 32;
     const int64_t blks_per_snr = (a.N + sym_per_blk - 1) / sym_per_blk;
     const int64_t total = blks_per_snr * a.n_snr;
+    // GMI / MI terms accumulate per lane in FP64 (fixed order: the blocks' symbol tiles are
+    // assigned statically) and are summed over the wave only when the SNR point changes.
     double gsum = 0.0, msum = 0.0;
     int cur = -1;
+    auto flush = [&]() {
+        const double gw = wave_sum(gsum), mw = wave_sum(msum);
+        if (lane == 0) {
+            acc_add(k.acc, cur, wave_slot, 0, gw);
+            acc_add(k.acc, cur, wave_slot, 1, mw);
+        }
+    };
+    // (s_idx, r) = divmod(bt, blks_per_snr), advanced incrementally (no 64-bit division per tile).
+    int s_idx = (int)(blockIdx.x / blks_per_snr);
+    int64_t r = blockIdx.x - (int64_t)s_idx * blks_per_snr;
     for (int64_t bt = blockIdx.x; bt < total; bt += gridDim.x) {
-        const int s_idx = (int)(bt / blks_per_snr);
-        const int64_t n = (bt % blks_per_snr) * sym_per_blk + wave * 32 + (lane & 31);
+        const int64_t n = r * sym_per_blk + wave * 32 + (lane & 31);
         if (s_idx != cur) {
-            if (cur >= 0 && k.acc && lane == 0) {
-                acc_add(k.acc, cur, wave_slot, 0, gsum);
-                acc_add(k.acc, cur, wave_slot, 1, msum);
-            }
+            if (cur >= 0 && k.acc) flush();
             gsum = msum = 0.0;
             cur = s_idx;
         }
@@ -76,15 +84,17 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
         }
         float g, mi;
         mfma_epilogue<T, D, SPLIT>(b, k, pv, bfr, A, n, active, bad, lane, g, mi);
-        if (k.acc) {
-            gsum += wave_sum(active ? (double)g : 0.0);
-            msum += wave_sum(active ? (double)mi : 0.0);
+        if (k.acc && active) {
+            gsum += (double)g;
+            msum += (double)mi;
+        }
+        r += gridDim.x;
+        while (r >= blks_per_snr) {
+            r -= blks_per_snr;
+            ++s_idx;
         }
     }
-    if (cur >= 0 && k.acc && lane == 0) {
-        acc_add(k.acc, cur, wave_slot, 0, gsum);
-        acc_add(k.acc, cur, wave_slot, 1, msum);
-    }
+    if (cur >= 0 && k.acc) flush();
 }
 
 template <typename T, int D, bool SPLIT>

@@ -86,6 +86,27 @@ __device__ __forceinline__ T round_pinned(float v) {
     return (T)v;
 }
 
+// v_permlane32_swap of two registers: afterwards lane i < 32 holds (a[i], a[i+32]) and lane
+// i + 32 holds (b[i], b[i+32]) in (r0, r1).  So r0 + r1 is a's two-half total in the lower half
+// of the wave and b's in the upper half, without an LDS round trip.
+__device__ __forceinline__ void swap_halves(uint32_t a, uint32_t b, uint32_t& r0, uint32_t& r1) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    r0 = r[0];
+    r1 = r[1];
+}
+
+__device__ __forceinline__ float half_pair_sum(float a, float b) {
+    uint32_t r0, r1;
+    swap_halves(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b), r0, r1);
+    return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+
+__device__ __forceinline__ uint32_t half_or(uint32_t a) {
+    uint32_t r0, r1;
+    swap_halves(a, a, r0, r1);
+    return r0 | r1;
+}
+
 // Builds this lane's symbol-side operand fragments: MFMA s, lane half h, values v = 0..7
 // cover slot k = 16 s + 8 h + v.
 template <typename T, int S>
@@ -281,20 +302,18 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
         S0[p] = hi0[p - 9];
         S1[p] = hi1[p - 9];
     }
-    // Exchange with the partner lane: half h keeps bit 2j + h of every pair (2j, 2j+1) and
-    // sends the partner its partial sums of the other bit.
+    // Combine with the partner lane: half h finishes bit 2j + h of every pair (2j, 2j+1) as
+    // its own partial sum plus the partner's.
     float c0[8], c1[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (2 * j < m) {
-            const float o0 = h ? S0[2 * j + 1] : S0[2 * j], o1 = h ? S1[2 * j + 1] : S1[2 * j];
-            const float x0 = h ? S0[2 * j] : S0[2 * j + 1], x1 = h ? S1[2 * j] : S1[2 * j + 1];
-            c0[j] = o0 + __shfl_xor(x0, 32, 64);
-            c1[j] = o1 + __shfl_xor(x1, 32, 64);
+            c0[j] = half_pair_sum(S0[2 * j], S0[2 * j + 1]);
+            c1[j] = half_pair_sum(S1[2 * j], S1[2 * j + 1]);
         }
     }
-    const bool bad_sym = bad || __shfl_xor((int)bad, 32, 64);
-    const float stot = tot + __shfl_xor(tot, 32, 64);
+    const bool bad_sym = half_or((uint32_t)bad) != 0;
+    const float stot = half_pair_sum(tot, tot);
 
     const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
     g = 0.0f;
@@ -308,7 +327,7 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
         if (2 * j < m) {
             const int p = 2 * j + h;
             const float s0 = c0[j], s1 = c1[j];
-            if (p < m) {
+            if (2 * j + 1 < m || h == 0) {  // p < m, written as a uniform test or the half-0 mask
                 if (!bad_sym && fminf(s0, s1) >= b.flag_thresh && fmaxf(s0, s1) < 3.0e38f) {
                     const float L = log2_ratio(s1, s0);
                     if (out) out[m - 1 - p] = L * 0.69314718055994531f;
@@ -348,12 +367,16 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
         for (int s2 = 1; s2 < S; ++s2)
             dg = Mma<T>::run(__builtin_bit_cast(V, *(const uint4*)(pr + 16 * s2)), bfr.v[s2], dg);
         const int j = lane & 31;
-        const int rd = 4 * (j >> 3) + (j & 3);
+        int rd = 4 * (j >> 3) + (j & 3);
+        asm volatile("" : "+v"(rd));  // keeps the 15 lane masks below from being hoisted out of the loop
         float v = dg[0];
 #pragma unroll
         for (int r = 1; r < 16; ++r) v = (rd == r) ? dg[r] : v;
-        const float vo = __shfl_xor(v, 32, 64);
-        const float ttx = (((j >> 2) & 1) == h) ? v : vo;
+        // The lane half (j >> 2) & 1 holds the diagonal element; after the swap it is r1 if
+        // that half is the upper one, else r0, in both halves.
+        uint32_t v0, v1;
+        swap_halves(__builtin_bit_cast(uint32_t, v), __builtin_bit_cast(uint32_t, v), v0, v1);
+        const float ttx = __builtin_bit_cast(float, ((j >> 2) & 1) ? v1 : v0);
         if (h == 0) {
             if (!bad_sym && stot >= b.flag_thresh && stot < 3.0e38f) {
                 const int e = __builtin_amdgcn_frexp_expf(stot);
@@ -364,7 +387,7 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
             }
         }
     }
-    mask |= (uint32_t)__shfl_xor((int)mask, 32, 64);
+    mask = half_or(mask);
     if (mask && active && h == 0) {
         double gc = 0.0, mc = 0.0;
         queue_or_fix<D>(b, k, (uint32_t)n, mask, gc, mc);
