@@ -64,9 +64,14 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
         }
         const bool active = n < a.N;
         const BlockView b = view_sym(a, s_idx, n, active);
+        // Inactive lanes (ragged tail) read row 0 and zero it: unconditional loads, no branches.
+        const float* yrow = b.y + (size_t)(active ? n : 0) * D;
         float y[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) y[d] = active ? b.y[(size_t)n * D + d] : 0.0f;
+        for (int d = 0; d < D; ++d) {
+            const float v = yrow[d];
+            y[d] = active ? v : 0.0f;
+        }
         bool bad = false;
         const Frags<T, S> bfr = build_symbol_frags<T, D, SPLIT>(y, b.c, b.K, h, bad);
 

@@ -329,9 +329,10 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
             const float s0 = c0[j], s1 = c1[j];
             if (2 * j + 1 < m || h == 0) {  // p < m, written as a uniform test or the half-0 mask
                 if (!bad_sym && fminf(s0, s1) >= b.flag_thresh && fmaxf(s0, s1) < 3.0e38f) {
-                    const float L = log2_ratio(s1, s0);
+                    float gb;
+                    const float L = llr_gmi(s0, s1, (txl >> p) & 1, gb);
                     if (out) out[m - 1 - p] = L * 0.69314718055994531f;
-                    g += gmi_bit_term(L, (txl >> p) & 1);
+                    g += gb;
                 } else {
                     flagged |= 1u << p;
                 }
