@@ -136,12 +136,12 @@ __global__ void zero_words(uint32_t* p, size_t n) {
 template <typename T, bool SPLIT>
 hipError_t prepare_t() {
     return hipFuncSetAttribute((const void*)demap_batched_kernel<T, SPLIT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kBatchedLdsBytes);
+                               kBatchedLdsAlloc);
 }
 
 template <typename T, bool SPLIT>
 hipError_t launch_batched_t(const BatchArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((demap_batched_kernel<T, SPLIT>), dim3(grid), dim3(kThreads), kBatchedLdsBytes, st, a);
+    hipLaunchKernelGGL((demap_batched_kernel<T, SPLIT>), dim3(grid), dim3(kThreads), kBatchedLdsAlloc, st, a);
     return hipGetLastError();
 }
 

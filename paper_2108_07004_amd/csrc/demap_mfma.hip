@@ -107,7 +107,7 @@ hipError_t launch_t(const LaunchArgs& a, const void* frag, const void* pv, int g
     constexpr int S = Slots<D, SPLIT>::S;
     const int ntiles = a.M >> 5;
     const int chunk_tiles = std::min(ntiles, kMfmaLdsBytes / (S * 64 * 16));
-    const size_t lds = (size_t)chunk_tiles * S * 64 * 16;
+    const size_t lds = (size_t)mfma_lds_tiles(chunk_tiles) * S * 64 * 16;
     auto kern = demap_mfma_kernel<T, D, SPLIT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -83,7 +83,10 @@ struct LaunchArgs {
 // ---- batched launch over many instances ----
 constexpr int kKindValu = 0;  // FP32 direct-difference body
 constexpr int kKindMfma = 1;  // MFMA cross-term body
-constexpr int kBatchedLdsBytes = 131072;
+constexpr int kBatchedLdsBytes = 131072;  // largest staged table (FP32 rows or MFMA fragments)
+// Dynamic LDS of the batched kernel: the table plus the one 2 KiB fragment tile (split
+// operands) that the MFMA pipeline reads past a 16-tile block.
+constexpr int kBatchedLdsAlloc = kBatchedLdsBytes + 2048;
 
 struct BatchDesc {             // one instance (device memory); view.tag = instance index
     BlockView view;            // table: FP32 label order with row stride 8

@@ -181,6 +181,10 @@ struct MfmaAcc {
     }
 };
 
+// Tiles the LDS copy of a cnt-tile chunk must span: the pipeline in mfma_tiles reads one
+// tile past each 16-tile block (that read is never consumed).
+constexpr int mfma_lds_tiles(int cnt) { return ((cnt + 15) / 16) * 16 + 1; }
+
 // Tiles [0, cnt) of the fragment table staged at lds_frag, global tile index t0 + t (t0 a
 // multiple of 16), against this wave's 32 symbols (operand fragments bfr).
 template <typename T, int D, bool SPLIT>
@@ -195,8 +199,10 @@ __device__ __forceinline__ void mfma_tiles(const uint4* lds_frag, int lane, int 
     float (&hi1)[7] = A.hi1;
     // Software pipeline: the MFMAs of tile t+1 are issued before the exp2s of tile t.
     // Even tiles use acc0, odd tiles acc1 (no register copies); the next-tile MFMA is
-    // unconditional (index clamped), only the consumption is guarded.  Blocks of 16
-    // tiles (512 labels) are unrolled so that label bits 5-6 index accB and 7-8 accC.
+    // unconditional, only the consumption is guarded.  Blocks of 16 tiles (512 labels) are
+    // unrolled so that label bits 5-6 index accB and 7-8 accC, and tile t+1 is read at a
+    // constant offset from the block's base address: the staged table must therefore extend
+    // to tile roundup(cnt, 16) (mfma_lds_tiles), whose contents are never consumed.
     auto tile_mma = [&](int t) {
         const uint4* fp = lds_frag + (size_t)t * S * 64 + lane;
         f32x16 acc = Mma<T>::run(__builtin_bit_cast(V, fp[0]), bfr.v[0]);
@@ -213,7 +219,6 @@ __device__ __forceinline__ void mfma_tiles(const uint4* lds_frag, int lane, int 
         return (((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]))) +
                (((e[8] + e[9]) + (e[10] + e[11])) + ((e[12] + e[13]) + (e[14] + e[15])));
     };
-    const int last = cnt - 1;
     f32x16 acc0 = tile_mma(0), acc1;
     for (int b0 = 0; b0 < cnt; b0 += 16) {
         float bt = 0.0f;
@@ -224,14 +229,14 @@ __device__ __forceinline__ void mfma_tiles(const uint4* lds_frag, int lane, int 
             for (int u = 0; u < 4; ++u) {
                 const int t = b0 + 4 * q + u;
                 if (u % 2 == 0) {
-                    acc1 = tile_mma(min(t + 1, last));
+                    acc1 = tile_mma(t + 1);
                     if (t < cnt) {
                         const float T16 = consume(acc0);
                         accB[u] += T16;
                         gt += T16;
                     }
                 } else {
-                    acc0 = tile_mma(min(t + 1, last));
+                    acc0 = tile_mma(t + 1);
                     if (t < cnt) {
                         const float T16 = consume(acc1);
                         accB[u] += T16;
