@@ -90,11 +90,13 @@ __global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a) {
     const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * 4;
     const int slot = (int)(wave % kAccSlots);
+    __shared__ float s_t[4][kFixCached];  // per-wave exponent cache (32 KiB per block)
+    float* tl = s_t[threadIdx.x >> 6];
     for (uint32_t i = wave; i < count; i += nwaves) {
         const FixEntry e = k.queue[i];
         const BlockView b = view_sym(a, (int)e.tag, e.n, true);
         double gc = 0.0, mc = 0.0;
-        fixup_wave<DP>(b, k, e.n, e.mask, gc, mc);
+        fixup_wave<DP>(b, k, e.n, e.mask, tl, gc, mc);
         if (k.acc && (threadIdx.x & 63) == 0) {
             acc_add(k.acc, (int)e.tag, slot, 0, gc);
             acc_add(k.acc, (int)e.tag, slot, 1, mc);

@@ -308,19 +308,53 @@ __device__ float wave_exact_llr2(const float (&y)[DP], const float* table, int M
     return (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
 }
 
+// Exponents t_j = K - c ||y - x_j||^2 of the queued symbol, cached in the wave's LDS slice
+// when M <= kFixCached (each lane keeps its own points j = lane + 64 i), so that each flagged
+// bit costs one max pass and one exp2 pass over the cache instead of two passes of distance
+// arithmetic.  The per-lane order of points and the wave reductions are those of
+// wave_exact_llr2: same results.
+constexpr int kFixCached = 2048;
+
+__device__ __forceinline__ float cached_exact_llr2(const float* tl, int M, int p, float& lse0) {
+    const int lane = threadIdx.x & 63;
+    float mx0 = -INFINITY, mx1 = -INFINITY;
+    for (int j = lane; j < M; j += 64) {
+        const float t = tl[j];
+        if (p >= 0 && ((j >> p) & 1)) mx1 = fmaxf(mx1, t);
+        else mx0 = fmaxf(mx0, t);
+    }
+    mx0 = wave_max_f(mx0);
+    mx1 = wave_max_f(mx1);
+    float s0 = 0.0f, s1 = 0.0f;
+    for (int j = lane; j < M; j += 64) {
+        const float t = tl[j];
+        if (p >= 0 && ((j >> p) & 1)) s1 += hw_exp2(t - mx1);
+        else s0 += hw_exp2(t - mx0);
+    }
+    s0 = wave_sum_f(s0);
+    s1 = wave_sum_f(s1);
+    lse0 = mx0 + hw_log2(s0);
+    return (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
+}
+
 // Recompute the flagged bits (and the MI term if asked) of one queued symbol with a whole
-// wavefront; lane 0 receives the GMI-term and MI-term corrections.
+// wavefront; lane 0 receives the GMI-term and MI-term corrections.  tl: this wave's LDS slice
+// of kFixCached floats.
 template <int DP>
-__device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask, double& gcorr,
+__device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask, float* tl, double& gcorr,
                            double& mcorr) {
     const int lane = threadIdx.x & 63;
     float y[DP];
     load_symbol<DP>(y, b.y + (size_t)n * b.D, b.D, true);
     const int txl = b.tx ? tx_label(b, k, n) : 0;
+    const bool cached = b.M <= kFixCached;  // uniform
+    if (cached)
+        for (int j = lane; j < b.M; j += 64) tl[j] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)j * DP), b.K);
     for (int p = 0; p < b.m; ++p) {
         if (!((mask >> p) & 1u)) continue;
         float lse0;
-        const float L = wave_exact_llr2<DP>(y, b.table, b.M, p, b.c, b.K, lse0);
+        const float L = cached ? cached_exact_llr2(tl, b.M, p, lse0)
+                               : wave_exact_llr2<DP>(y, b.table, b.M, p, b.c, b.K, lse0);
         if (lane == 0) {
             if (b.llr) b.llr[(size_t)n * b.m + (b.m - 1 - p)] = L * 0.69314718055994531f;
             if (b.tx) gcorr += (double)gmi_bit_term(L, (txl >> p) & 1);
@@ -328,7 +362,8 @@ __device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint3
     }
     if ((mask & kMiFlag) && b.tx) {
         float lse_all;
-        (void)wave_exact_llr2<DP>(y, b.table, b.M, -1, b.c, b.K, lse_all);
+        if (cached) (void)cached_exact_llr2(tl, b.M, -1, lse_all);
+        else (void)wave_exact_llr2<DP>(y, b.table, b.M, -1, b.c, b.K, lse_all);
         const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
         if (lane == 0) mcorr += (double)((float)b.m - (lse_all - ttx));
     }
