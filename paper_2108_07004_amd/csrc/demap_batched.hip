@@ -108,25 +108,10 @@ __global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs
     }
 }
 
-// One wavefront per queued symbol of any instance.
+// Exact recomputation of the queued symbols of every instance (one lane or one wavefront per symbol).
 __global__ __launch_bounds__(256) void batched_fixup_kernel(const BatchArgs a) {
-    const Sinks& k = a.sinks;
-    const uint32_t count = min(*k.queue_count, k.queue_cap);
-    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint32_t nwaves = gridDim.x * 4;
-    const int slot = (int)(wave % kAccSlots);
     __shared__ float s_t[4][kFixCached];  // per-wave exponent cache (32 KiB per block)
-    float* tl = s_t[threadIdx.x >> 6];
-    for (uint32_t i = wave; i < count; i += nwaves) {
-        const FixEntry e = k.queue[i];
-        const BlockView b = a.desc[e.tag].view;
-        double gc = 0.0, mc = 0.0;
-        fixup_wave<8>(b, k, e.n, e.mask, tl, gc, mc);
-        if (k.acc && (threadIdx.x & 63) == 0) {
-            acc_add(k.acc, (int)e.tag, slot, 0, gc);
-            acc_add(k.acc, (int)e.tag, slot, 1, mc);
-        }
-    }
+    drain_fix_queue<8>(a.sinks, [&](const FixEntry& e) { return a.desc[e.tag].view; }, s_t[threadIdx.x >> 6]);
 }
 
 // Zero the accumulators and counters with a kernel (a graph must not hold memset nodes).

@@ -82,26 +82,12 @@ __global__ __launch_bounds__(kValuThreads) void demap_valu_kernel(const LaunchAr
     }
 }
 
-// One wavefront per queued symbol (grid-stride over the queue).
+// Exact recomputation of the queued symbols (one lane or one wavefront per symbol).
 template <int DP>
 __global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a) {
-    const Sinks& k = a.sinks;
-    const uint32_t count = min(*k.queue_count, k.queue_cap);
-    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint32_t nwaves = gridDim.x * 4;
-    const int slot = (int)(wave % kAccSlots);
     __shared__ float s_t[4][kFixCached];  // per-wave exponent cache (32 KiB per block)
-    float* tl = s_t[threadIdx.x >> 6];
-    for (uint32_t i = wave; i < count; i += nwaves) {
-        const FixEntry e = k.queue[i];
-        const BlockView b = view_sym(a, (int)e.tag, e.n, true);
-        double gc = 0.0, mc = 0.0;
-        fixup_wave<DP>(b, k, e.n, e.mask, tl, gc, mc);
-        if (k.acc && (threadIdx.x & 63) == 0) {
-            acc_add(k.acc, (int)e.tag, slot, 0, gc);
-            acc_add(k.acc, (int)e.tag, slot, 1, mc);
-        }
-    }
+    drain_fix_queue<DP>(a.sinks, [&](const FixEntry& e) { return view_sym(a, (int)e.tag, e.n, true); },
+                        s_t[threadIdx.x >> 6]);
 }
 
 template <int DP>

@@ -369,6 +369,49 @@ __device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint3
     }
 }
 
+// Drain the fix-up queue: symbols of constellations with at most kFixLaneMaxM points are
+// recomputed one per lane (fixup_one: cheaper than wave reductions for so few points), the
+// others one per wavefront (fixup_wave).  view(e) gives the block of a queue entry; tl is the
+// wave's LDS slice.  Corrections go to the fixed-point accumulators (slot = lane in the lane
+// pass, wave % kAccSlots in the wave pass).
+constexpr int kFixLaneMaxM = 64;
+
+template <int DP, typename ViewFn>
+__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl) {
+    const uint32_t count = min(*k.queue_count, k.queue_cap);
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
+        const uint32_t i = base + lane;
+        if (i < count) {
+            const FixEntry e = k.queue[i];
+            const BlockView b = view(e);
+            if (b.M <= kFixLaneMaxM) {
+                double gc = 0.0, mc = 0.0;
+                fixup_one<DP>(b, k, e.n, e.mask, gc, mc);
+                if (k.acc) {
+                    acc_add(k.acc, (int)e.tag, lane, 0, gc);
+                    acc_add(k.acc, (int)e.tag, lane, 1, mc);
+                }
+            }
+        }
+    }
+    const int slot = (int)(wave % kAccSlots);
+    for (uint32_t i = wave; i < count; i += nwaves) {
+        const FixEntry e = k.queue[i];
+        const BlockView b = view(e);
+        if (b.M > kFixLaneMaxM) {
+            double gc = 0.0, mc = 0.0;
+            fixup_wave<DP>(b, k, e.n, e.mask, tl, gc, mc);
+            if (k.acc && lane == 0) {
+                acc_add(k.acc, (int)e.tag, slot, 0, gc);
+                acc_add(k.acc, (int)e.tag, slot, 1, mc);
+            }
+        }
+    }
+}
+
 // Queue a symbol for the fix-up; when the queue is full the calling lane recomputes it in
 // place (slow but exact) and the corrections come back through gc / mc.
 template <int DP>
