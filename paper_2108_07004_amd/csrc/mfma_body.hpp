@@ -336,7 +336,13 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
                 if (!bad_sym && fminf(s0, s1) >= b.flag_thresh && fmaxf(s0, s1) < 3.0e38f) {
                     float gb;
                     const float L = llr_gmi(s0, s1, (txl >> p) & 1, gb);
-                    if (out) out[m - 1 - p] = L * 0.69314718055994531f;
+                    if (out) {
+                        // The column is formed from an opaque copy of h, so that the compiler
+                        // recomputes it here instead of keeping 8 per-lane offsets live (they spilled).
+                        int hv = h;
+                        asm volatile("" : "+v"(hv));
+                        out[m - 1 - 2 * j - hv] = L * 0.69314718055994531f;
+                    }
                     g += gb;
                 } else {
                     flagged |= 1u << p;
