@@ -378,6 +378,22 @@ constexpr int kFixLaneMaxM = 64;
 
 template <int DP, typename ViewFn>
 __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl) {
+    // Corrections of blocks (tags) below kFixLdsTags are summed per workgroup in LDS, as the same
+    // fixed-point integers acc_add uses (so the totals are unchanged and order-independent), and
+    // flushed once per workgroup: per-entry global atomics were the fix-up's bottleneck.
+    constexpr int kFixLdsTags = 64;
+    __shared__ unsigned long long s_acc[kFixLdsTags * 2];
+    for (int i = threadIdx.x; i < kFixLdsTags * 2; i += blockDim.x) s_acc[i] = 0ull;
+    __syncthreads();
+    auto add = [&](int tag, int slot, int which, double v) {
+        if (!k.acc) return;
+        if (tag < kFixLdsTags) {
+            const long long q = __double2ll_rn(v * kFixScale);
+            if (q != 0) atomicAdd(&s_acc[tag * 2 + which], (unsigned long long)q);
+        } else {
+            acc_add(k.acc, tag, slot, which, v);
+        }
+    };
     const uint32_t count = min(*k.queue_count, k.queue_cap);
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -390,10 +406,8 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl) {
             if (b.M <= kFixLaneMaxM) {
                 double gc = 0.0, mc = 0.0;
                 fixup_one<DP>(b, k, e.n, e.mask, gc, mc);
-                if (k.acc) {
-                    acc_add(k.acc, (int)e.tag, lane, 0, gc);
-                    acc_add(k.acc, (int)e.tag, lane, 1, mc);
-                }
+                add((int)e.tag, lane, 0, gc);
+                add((int)e.tag, lane, 1, mc);
             }
         }
     }
@@ -404,11 +418,17 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl) {
         if (b.M > kFixLaneMaxM) {
             double gc = 0.0, mc = 0.0;
             fixup_wave<DP>(b, k, e.n, e.mask, tl, gc, mc);
-            if (k.acc && lane == 0) {
-                acc_add(k.acc, (int)e.tag, slot, 0, gc);
-                acc_add(k.acc, (int)e.tag, slot, 1, mc);
+            if (lane == 0) {
+                add((int)e.tag, slot, 0, gc);
+                add((int)e.tag, slot, 1, mc);
             }
         }
+    }
+    __syncthreads();
+    if (k.acc) {
+        const int bslot = (int)(blockIdx.x % kAccSlots);
+        for (int i = threadIdx.x; i < kFixLdsTags * 2; i += blockDim.x)
+            if (s_acc[i] != 0ull) atomicAdd(k.acc + ((size_t)(i >> 1) * kAccSlots + bslot) * 2 + (i & 1), s_acc[i]);
     }
 }
 
