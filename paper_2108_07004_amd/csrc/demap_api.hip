@@ -278,7 +278,7 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
     }
     DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
     const int grid = persistent_grid(c, tiles_per_snr * n_snr, prec == DM_PREC_FP32 ? 2 : 1);
-    const int fix_grid = c->cus * 4;
+    const int fix_grid = c->cus * dm::fixup_blocks_per_cu(c->M);
     ProfRec pr{nullptr, nullptr, nullptr};
     if (g_prof_on) {
         pr = ProfRec{prof_event(), prof_event(), prof_event()};

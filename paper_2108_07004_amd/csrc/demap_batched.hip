@@ -111,7 +111,8 @@ __global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs
 // Exact recomputation of the queued symbols of every instance (one lane or one wavefront per symbol).
 __global__ __launch_bounds__(256) void batched_fixup_kernel(const BatchArgs a) {
     __shared__ float s_t[4][kFixCached];  // per-wave exponent cache (32 KiB per block)
-    drain_fix_queue<8>(a.sinks, [&](const FixEntry& e) { return a.desc[e.tag].view; }, s_t[threadIdx.x >> 6]);
+    drain_fix_queue<8>(a.sinks, [&](const FixEntry& e) { return a.desc[e.tag].view; }, s_t[threadIdx.x >> 6],
+                       kFixCached);
 }
 
 // Zero the accumulators and counters with a kernel (a graph must not hold memset nodes).

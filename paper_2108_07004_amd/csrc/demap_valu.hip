@@ -84,10 +84,10 @@ __global__ __launch_bounds__(kValuThreads) void demap_valu_kernel(const LaunchAr
 
 // Exact recomputation of the queued symbols (one lane or one wavefront per symbol).
 template <int DP>
-__global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a) {
-    __shared__ float s_t[4][kFixCached];  // per-wave exponent cache (32 KiB per block)
+__global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a, int cache_pts) {
+    extern __shared__ float s_t[];  // per-wave exponent caches, 4 x cache_pts floats
     drain_fix_queue<DP>(a.sinks, [&](const FixEntry& e) { return view_sym(a, (int)e.tag, e.n, true); },
-                        s_t[threadIdx.x >> 6]);
+                        s_t + (threadIdx.x >> 6) * cache_pts, cache_pts);
 }
 
 template <int DP>
@@ -102,7 +102,7 @@ hipError_t launch_valu_t(const LaunchArgs& a, int grid, hipStream_t st) {
 
 template <int DP>
 hipError_t launch_fixup_t(const LaunchArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(fixup_kernel<DP>, dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(fixup_kernel<DP>, dim3(grid), dim3(256), fixup_lds_bytes(a.M), st, a, fixup_cache_points(a.M));
     return hipGetLastError();
 }
 

@@ -270,16 +270,36 @@ __device__ void fixup_one(const BlockView& b, const Sinks& k, uint32_t n, uint32
 
 // ---- wave-cooperative fix-up: one wavefront per queued symbol, lanes split the points ----
 
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+// Wave-wide max / sum of one float per lane, every lane receiving the result, in VALU only
+// (the whole wave must be active): v_permlane32_swap and v_permlane16_swap pair lanes 32 and 16
+// apart (the two outputs hold the pair in both lanes), then DPP row rotations by 8, 4, 2, 1
+// combine the 16 lanes of each row.  No LDS round trips on the fix-up's dependent chains.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+template <typename Op>
+__device__ __forceinline__ float wave_reduce_f(float v, Op op) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    v = op(__builtin_bit_cast(float, (uint32_t)a[0]), __builtin_bit_cast(float, (uint32_t)a[1]));
+    const uint32_t w = __builtin_bit_cast(uint32_t, v);
+    const auto b = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+    v = op(__builtin_bit_cast(float, (uint32_t)b[0]), __builtin_bit_cast(float, (uint32_t)b[1]));
+    v = op(v, dpp_f<0x128>(v));  // row_ror:8
+    v = op(v, dpp_f<0x124>(v));  // row_ror:4
+    v = op(v, dpp_f<0x122>(v));  // row_ror:2
+    v = op(v, dpp_f<0x121>(v));  // row_ror:1
     return v;
 }
 
+__device__ __forceinline__ float wave_max_f(float v) {
+    return wave_reduce_f(v, [](float x, float y) { return fmaxf(x, y); });
+}
+
 __device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return wave_reduce_f(v, [](float x, float y) { return x + y; });
 }
 
 // Exact subset log-sum-exps of label bit p (p < 0: all points into subset 0) for one symbol,
@@ -339,15 +359,15 @@ __device__ __forceinline__ float cached_exact_llr2(const float* tl, int M, int p
 
 // Recompute the flagged bits (and the MI term if asked) of one queued symbol with a whole
 // wavefront; lane 0 receives the GMI-term and MI-term corrections.  tl: this wave's LDS slice
-// of kFixCached floats.
+// of cache_pts (<= kFixCached) floats.
 template <int DP>
-__device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask, float* tl, double& gcorr,
-                           double& mcorr) {
+__device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask, float* tl, int cache_pts,
+                           double& gcorr, double& mcorr) {
     const int lane = threadIdx.x & 63;
     float y[DP];
     load_symbol<DP>(y, b.y + (size_t)n * b.D, b.D, true);
     const int txl = b.tx ? tx_label(b, k, n) : 0;
-    const bool cached = b.M <= kFixCached;  // uniform
+    const bool cached = b.M <= cache_pts;  // uniform
     if (cached)
         for (int j = lane; j < b.M; j += 64) tl[j] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)j * DP), b.K);
     for (int p = 0; p < b.m; ++p) {
@@ -372,12 +392,12 @@ __device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint3
 // Drain the fix-up queue: symbols of constellations with at most kFixLaneMaxM points are
 // recomputed one per lane (fixup_one: cheaper than wave reductions for so few points), the
 // others one per wavefront (fixup_wave).  view(e) gives the block of a queue entry; tl is the
-// wave's LDS slice.  Corrections go to the fixed-point accumulators (slot = lane in the lane
+// wave's LDS slice of cache_pts floats.  Corrections go to the fixed-point accumulators (slot = lane in the lane
 // pass, wave % kAccSlots in the wave pass).
 constexpr int kFixLaneMaxM = 64;
 
 template <int DP, typename ViewFn>
-__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl) {
+__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cache_pts) {
     // Corrections of blocks (tags) below kFixLdsTags are summed per workgroup in LDS, as the same
     // fixed-point integers acc_add uses (so the totals are unchanged and order-independent), and
     // flushed once per workgroup: per-entry global atomics were the fix-up's bottleneck.
@@ -417,7 +437,7 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl) {
         const BlockView b = view(e);
         if (b.M > kFixLaneMaxM) {
             double gc = 0.0, mc = 0.0;
-            fixup_wave<DP>(b, k, e.n, e.mask, tl, gc, mc);
+            fixup_wave<DP>(b, k, e.n, e.mask, tl, cache_pts, gc, mc);
             if (lane == 0) {
                 add((int)e.tag, slot, 0, gc);
                 add((int)e.tag, slot, 1, mc);

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 
 namespace dm {
@@ -26,6 +28,11 @@ hipError_t launch_demap_valu(const LaunchArgs& a, int grid, hipStream_t st);
 
 // Exact recomputation of the queued (symbol, bit) pairs whose far-subset sum underflowed.
 hipError_t launch_fixup(const LaunchArgs& a, int grid, hipStream_t st);
+// Exponent cache of the fix-up kernel (per wave, 4 waves per block) for an M-point constellation,
+// and the blocks per CU that fit it within 160 KiB of LDS and the kernel's 8 waves per SIMD.
+inline int fixup_cache_points(int M) { return M <= kFixCached ? ((M + 63) / 64) * 64 : 64; }
+inline size_t fixup_lds_bytes(int M) { return (size_t)4 * fixup_cache_points(M) * sizeof(float); }
+inline int fixup_blocks_per_cu(int M) { return (int)std::min<size_t>(8, (160 * 1024) / (fixup_lds_bytes(M) + 1024)); }
 
 // K slots (multiple of 16) of the MFMA operand vectors for dimensionality D.
 int mfma_slots(int D, bool split);
