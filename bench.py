@@ -13,6 +13,7 @@ against the exp2 issue rate: the exact log-sum-exp needs M exponentials per symb
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -210,6 +211,54 @@ def bench_hard(const, w, ys, tx_t, steps, method="auto"):
             "q_db": [None if not (0 < b < 0.5) else round(dm.q_factor_db(float(b)), 3) for b in ber]}
 
 
+def bench_configs(steps=10, warmup=2):
+    """The smaller parity workloads timed like the headline: DP-QPSK (FP32: 16 points) and
+    DP-16QAM (FP32 and fp16x3), inputs resident in HBM, LLRs + GMI + MI, demap and fix-up
+    kernel times from the library's own events."""
+    import torch
+
+    import paper_2108_07004_amd as dm
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, precs in (("dpqpsk", ("fp32",)), ("dp16qam", ("fp32", "fp16x3"))):
+        w = W.workload(name)
+        tx, z = W.workload_tx_noise(w)
+        tx_t = torch.from_numpy(tx.view(np.int16)).to(dev)
+        z_t = torch.from_numpy(z).to(dev)
+        ys = [W.awgn_torch(w.const.points, tx_t, z_t, s2) for s2 in w.sigma2]
+        del z_t
+        llrs = [torch.empty((w.N, w.const.m), dtype=torch.float32, device=dev) for _ in w.sigma2]
+        const = dm.Constellation(w.const.points, w.const.labels)
+        for prec in precs:
+            for _ in range(warmup):
+                dm.gmi_estimate(const, w.sigma2, ys, tx_t, llrs, prec=prec)
+            torch.cuda.synchronize()
+            dm.profile_enable(True)
+            dm.profile_read(reset=True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                gmi, _ = dm.gmi_estimate(const, w.sigma2, ys, tx_t, llrs, prec=prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            main_ms, fix_ms, launches = dm.profile_read(reset=True)
+            dm.profile_enable(False)
+            fix_total, _ = dm.last_fixup_count(len(w.sigma2))
+            n_sym = w.N * len(w.sigma2)
+            pairs = float(n_sym) * w.const.M
+            res[f"{name}/{prec}"] = {
+                "workload": f"{w.name}: M={w.const.M} D={w.const.D} N={w.N} x {len(w.sigma2)} SNR "
+                            f"{w.snr_db[0]:g}..{w.snr_db[-1]:g} dB, LLRs + GMI + MI",
+                "symbols_per_s": n_sym / dt, "ms_per_step": dt * 1e3,
+                "demap_ms": main_ms / max(launches, 1), "fixup_ms": fix_ms / max(launches, 1),
+                "fixup_pairs": int(fix_total),
+                "exp2_frac_of_peak": pairs / (main_ms * 1e-3 / max(launches, 1)) / (FULL_RATE / EXP2_ISSUE_CYCLES),
+                "gmi": [round(float(v), 6) for v in gmi]}
+        del ys, llrs
+    return res
+
+
 def bench_stream(const, w, ys, prec, buffer_symbols=1 << 20, n_buffers=3):
     """Host-to-host streamed demapping of one received block (PCIe transfers included)."""
     import torch
@@ -277,6 +326,7 @@ def main():
     ap.add_argument("--no-hard", action="store_true", help="skip the hard-decision measurement")
     ap.add_argument("--hard-method", default="auto", choices=["auto", "valu", "mfma"],
                     help="hard-decision method (auto: MFMA ranking where it applies)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the DP-QPSK / DP-16QAM workloads")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-to-host streamed measurement")
     ap.add_argument("--no-gs", action="store_true", help="skip the shaping-search measurement")
     ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
@@ -295,6 +345,11 @@ def main():
     import paper_2108_07004_amd as dm
     import workloads as W
 
+    # Timed loops of a few milliseconds per step must not absorb a cyclic-garbage collection
+    # pause of the interpreter (tens of ms, seen on the DP-16QAM loop): collect now, then
+    # leave the collector off for the run.
+    gc.collect()
+    gc.disable()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = W.workload(args.workload)
@@ -385,6 +440,12 @@ def main():
         out["batched"] = bench_batched(args.prec if args.prec != "fp32" else "fp16x3", max(3, args.steps), 2)
         log(f"batched: {out['batched']['ms_per_launch']:.3f} ms/launch, "
             f"{out['batched']['symbols_per_s'] / 1e9:.3f} Gsym/s")
+    if not args.no_configs:
+        log("configs: DP-QPSK and DP-16QAM parity workloads")
+        out["configs"] = bench_configs()
+        for k, v in out["configs"].items():
+            log(f"configs: {k} {v['symbols_per_s'] / 1e9:.3f} Gsym/s (demap {v['demap_ms']:.3f} ms, "
+                f"fix-up {v['fixup_ms']:.3f} ms per launch)")
     if not args.no_stream:
         log("streamed: host buffers in, host LLRs out")
         out["streamed"] = bench_stream(const, w, ys, args.prec)
