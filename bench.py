@@ -41,10 +41,10 @@ EXP2_ISSUE_CYCLES = 2  # v_exp_f32 issues at half the full FP32 rate on gfx950 (
 # 512 MiB device copy in the same runs.  Valid only for the kernel sources they were taken on.
 TRAFFIC_PMC = {
     "prec": "fp16x3", "workload": "gauss8d2048",
-    "bytes": (4479349 * 2 + 11547213) * 1024,
+    "bytes": (4481032 * 2 + 11547159) * 1024,
     "sources": ["paper_2108_07004_amd/csrc/demap_mfma.hip", "paper_2108_07004_amd/csrc/mfma_body.hpp",
                 "paper_2108_07004_amd/csrc/device_common.hpp"],
-    "sha256": "d609b7e768b792e4e8debd35efd30e79b4bd8097bd4e2d3eef8793e70fea98ab",
+    "sha256": "438a8221d24d61e6a9c23fe6640165d639bd30c82b7adfc42c2c145d66c06eaa",
 }
 
 
