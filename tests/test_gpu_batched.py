@@ -127,3 +127,29 @@ def test_plan_rejects_unsupported():
     c4 = dm.Constellation(W.dp_qpsk().points, W.dp_qpsk().labels)
     with pytest.raises(dm.DemapError):
         dm.Plan([(c4, 0.1, torch.zeros((8, 4), dtype=torch.float32, device="cuda:0"), None, None)], force="mfma")
+
+
+def test_fixups_of_instances_beyond_the_lds_tag_table():
+    """More than 64 instances, the last ones at high SNR on sparse 8D constellations, so that
+    fix-up corrections arrive for instance tags >= 64 (summed with global atomics instead of the
+    workgroup's LDS table) as well as below it, by lanes (M <= 64) and by wavefronts (M = 256)."""
+    import torch
+    insts = W.batched_instances(64, n_lo=7, n_hi=9)
+    extra = [(16, 8, 19.0), (64, 8, 18.0), (256, 8, 17.0), (16, 8, 16.0), (64, 8, 20.0), (256, 8, 19.5)]
+    for k, (M, D, snr) in enumerate(extra):
+        i = 64 + k
+        insts.append(W.Instance(i, W.gaussian_constellation(M, D, 3, i), 700 + 37 * k, snr))
+    items, host, _ = _build(insts)
+    plan = dm.Plan(items, prec="fp16x3", autotune=True)
+    kinds, _ = plan.info()
+    plan.launch()
+    gmi, mi, fx = plan.results()
+    torch.cuda.synchronize()
+    assert np.all(fx[64:] > 0), fx[64:]  # the high tags really went through the fix-up
+    for i, (inst, y, tx) in enumerate(host):
+        ref = oracle.demap(inst.const.points, inst.const.labels, inst.sigma2, y, tx)
+        got = items[i][4].cpu().numpy()
+        tol = LLR_TOL_FP32 if kinds[i] == 0 else LLR_TOL_MFMA_FP16X3
+        assert rel_err(got, ref["llr"]) <= tol, (i, inst.const.M, inst.const.D, inst.snr_db)
+        assert abs(gmi[i] - ref["gmi"]) <= GMI_TOL, (i, gmi[i], ref["gmi"])
+        assert abs(mi[i] - ref["mi_mean"]) <= GMI_TOL, (i, mi[i], ref["mi_mean"])
