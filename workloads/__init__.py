@@ -106,6 +106,25 @@ def product_pam(levels: int, D: int, name: str) -> Constellation:
     return Constellation(pts, lab.astype(np.uint16), name)
 
 
+def product_pam_mixed(levels: list, name: str = "") -> Constellation:
+    """Product of BRGC-labelled PAMs with levels[d] points in dimension d, each scaled so that
+    E x_d^2 = 1/2 (unit energy per 2D); rows in ascending lexicographic amplitude order, label =
+    concatenated per-dimension BRGC labels, dimension 0 most significant.  With levels
+    (4, 4, 4, 2, 2, 2, 2, 2) it is an 8D, M = 2048 constellation whose bit LLRs each depend on one
+    coordinate (a structured counterpart of the random 8D constellation)."""
+    D = len(levels)
+    per = [pam_brgc(L) for L in levels]
+    qs = [int(round(math.log2(L))) for L in levels]
+    grids = np.stack(np.meshgrid(*[np.arange(L) for L in levels], indexing="ij"), axis=-1).reshape(-1, D)
+    pts = np.empty(grids.shape, dtype=np.float64)
+    lab = np.zeros(grids.shape[0], dtype=np.int64)
+    for d, (amps, glab) in enumerate(per):
+        scale = math.sqrt(1.0 / (2.0 * float(np.mean(amps * amps))))
+        pts[:, d] = amps[grids[:, d]] * scale
+        lab = (lab << qs[d]) | glab[grids[:, d]]
+    return Constellation(pts.astype(np.float32), lab.astype(np.uint16), name)
+
+
 def dp_qpsk() -> Constellation:
     """DP-QPSK: 4D, M=16, per-quadrature BRGC (bit 0 -> -A, 1 -> +A, A=1/sqrt2)."""
     return product_pam(2, 4, "dp-qpsk")
