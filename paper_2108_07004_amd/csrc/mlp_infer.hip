@@ -126,23 +126,28 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
         // Layer-2 weight fragments stream through a ring of kRing registers: the read of
         // fragment g + kRing is issued right after fragment g is consumed, so LDS latency
         // overlaps kRing - 1 MFMAs (the ring runs on across blocks; past the end it rereads the
-        // last fragment, which is never used).
+        // last fragment, which is never used).  The layer is software-pipelined over its 8 output
+        // blocks: while the 16 MFMAs of block b run, the wave evaluates block b-1's 16 GELUs, one
+        // per MFMA, and feeds them to layer 3 afterwards, so matrix and vector work overlap
+        // within the wave.
         bf16x8 ring[kRing];
 #pragma unroll
         for (int q = 0; q < kRing; ++q) ring[q] = __builtin_bit_cast(bf16x8, w2[q * 64 + lane]);
-#pragma unroll 1
-        for (int b = 0; b < 8; ++b) {
-            f32x16 acc2 = {};
+        auto l2_step = [&](int b, int ks, f32x16 acc) {
+            const bf16x8 cur = ring[ks % kRing];
+            const int next = min(b * 16 + ks + kRing, 8 * 16 - 1);
+            ring[ks % kRing] = __builtin_bit_cast(bf16x8, w2[next * 64 + lane]);
+            return __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur, a1[ks], acc, 0, 0, 0);
+        };
+        f32x16 accp = {};
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks) {
-                const bf16x8 cur = ring[ks % kRing];
-                const int next = min(b * 16 + ks + kRing, 8 * 16 - 1);
-                ring[ks % kRing] = __builtin_bit_cast(bf16x8, w2[next * 64 + lane]);
-                acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur, a1[ks], acc2, 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);  // keep the read kRing steps ahead of its use
-            }
-            // block b's biases and layer-3 fragments, read together (one LDS wait)
-            const float4* bb4 = reinterpret_cast<const float4*>(lbias + (b * 2 + h) * 16);
+        for (int ks = 0; ks < 16; ++ks) {
+            accp = l2_step(0, ks, accp);
+            __builtin_amdgcn_sched_barrier(0);  // keep the read kRing steps ahead of its use
+        }
+        // block p's GELUs feed layer 3; with `next` the MFMAs of block p + 1 run in between
+        auto finish = [&](int p, bool next, f32x16& accn) {
+            const float4* bb4 = reinterpret_cast<const float4*>(lbias + (p * 2 + h) * 16);
             float bb[16];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -152,18 +157,28 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
                 bb[4 * q + 2] = v.z;
                 bb[4 * q + 3] = v.w;
             }
-            const bf16x8 w3lo = __builtin_bit_cast(bf16x8, w3[(2 * b) * 64 + lane]);
-            const bf16x8 w3hi = __builtin_bit_cast(bf16x8, w3[(2 * b + 1) * 64 + lane]);
-            __builtin_amdgcn_sched_barrier(0);
+            const bf16x8 w3lo = __builtin_bit_cast(bf16x8, w3[(2 * p) * 64 + lane]);
+            const bf16x8 w3hi = __builtin_bit_cast(bf16x8, w3[(2 * p + 1) * 64 + lane]);
             bf16x8 lo, hi;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const __bf16 q = (__bf16)gelu_f(acc2[r] + bb[r]);
-                if (r < 8) lo[r] = q;
-                else hi[r - 8] = q;
+            for (int ks = 0; ks < 16; ++ks) {
+                if (next) accn = l2_step(p + 1, ks, accn);
+                const __bf16 q = (__bf16)gelu_f(accp[ks] + bb[ks]);
+                if (ks < 8) lo[ks] = q;
+                else hi[ks - 8] = q;
             }
             acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3lo, lo, acc3, 0, 0, 0);
             acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3hi, hi, acc3, 0, 0, 0);
+        };
+#pragma unroll 1
+        for (int b = 1; b < 8; ++b) {
+            f32x16 accn = {};
+            finish(b - 1, true, accn);
+            accp = accn;
+        }
+        {
+            f32x16 unused = {};
+            finish(7, false, unused);
         }
         // outputs: register r holds output o = 8 (r / 4) + 4 h + (r % 4) of symbol n
         int txl = 0;
