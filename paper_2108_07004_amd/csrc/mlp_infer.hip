@@ -139,7 +139,21 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
             ring[ks % kRing] = __builtin_bit_cast(bf16x8, w2[next * 64 + lane]);
             return __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur, a1[ks], acc, 0, 0, 0);
         };
-        f32x16 accp = {};
+        // Block p's layer-2 biases seed its accumulators (the MFMAs add onto them).
+        auto bias_acc = [&](int p) {
+            const float4* bb4 = reinterpret_cast<const float4*>(lbias + (p * 2 + h) * 16);
+            f32x16 acc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = bb4[q];
+                acc[4 * q] = v.x;
+                acc[4 * q + 1] = v.y;
+                acc[4 * q + 2] = v.z;
+                acc[4 * q + 3] = v.w;
+            }
+            return acc;
+        };
+        f32x16 accp = bias_acc(0);
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
             accp = l2_step(0, ks, accp);
@@ -147,23 +161,13 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
         }
         // block p's GELUs feed layer 3; with `next` the MFMAs of block p + 1 run in between
         auto finish = [&](int p, bool next, f32x16& accn) {
-            const float4* bb4 = reinterpret_cast<const float4*>(lbias + (p * 2 + h) * 16);
-            float bb[16];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float4 v = bb4[q];
-                bb[4 * q] = v.x;
-                bb[4 * q + 1] = v.y;
-                bb[4 * q + 2] = v.z;
-                bb[4 * q + 3] = v.w;
-            }
             const bf16x8 w3lo = __builtin_bit_cast(bf16x8, w3[(2 * p) * 64 + lane]);
             const bf16x8 w3hi = __builtin_bit_cast(bf16x8, w3[(2 * p + 1) * 64 + lane]);
             bf16x8 lo, hi;
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks) {
                 if (next) accn = l2_step(p + 1, ks, accn);
-                const __bf16 q = (__bf16)gelu_f(accp[ks] + bb[ks]);
+                const __bf16 q = (__bf16)gelu_f(accp[ks]);
                 if (ks < 8) lo[ks] = q;
                 else hi[ks - 8] = q;
             }
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
         };
 #pragma unroll 1
         for (int b = 1; b < 8; ++b) {
-            f32x16 accn = {};
+            f32x16 accn = bias_acc(b);
             finish(b - 1, true, accn);
             accp = accn;
         }
