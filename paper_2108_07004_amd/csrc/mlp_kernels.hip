@@ -111,23 +111,45 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
     }
 }
 
-// Row sums of a BF16 matrix (rows contiguous): out[row] = sum_b X[row][b]; one wave per row.
+// Row sums of a BF16 matrix (rows contiguous): out[row] = sum_b X[row][b].
 __global__ __launch_bounds__(256) void rowsum_kernel(const __bf16* X, int rows, int cols, int ld, float* out) {
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wave >= rows) return;
+    // One workgroup per row; 16-byte loads of 8 values when the row layout allows; fixed
+    // summation order (per thread, then the wave butterfly, then the 4 waves in order).
+    const int row = blockIdx.x;
+    if (row >= rows) return;
+    const __bf16* xr = X + (size_t)row * ld;
     float s = 0.0f;
-    for (int b = lane; b < cols; b += 64) s += (float)X[(size_t)wave * ld + b];
+    const bool vec = (cols % 8 == 0) && (ld % 8 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+    if (vec) {
+        for (int c = threadIdx.x * 8; c < cols; c += blockDim.x * 8) {
+            const bf16x8 v = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(xr + c));
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += (float)v[q];
+        }
+    } else {
+        for (int c = threadIdx.x; c < cols; c += blockDim.x) s += (float)xr[c];
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) out[wave] = s;
+    __shared__ float part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[row] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // grad[idx] = sum over splits (fixed order) of part[s][idx] for idx < n.
 __global__ void reduce_splits_kernel(const float* part, int splits, size_t n, float* grad) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         float s = 0.0f;
-        for (int k = 0; k < splits; ++k) s += part[(size_t)k * n + i];
+        int k = 0;
+        for (; k + 8 <= splits; k += 8) {  // eight loads in flight, added in split order
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = part[(size_t)(k + q) * n + i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += v[q];
+        }
+        for (; k < splits; ++k) s += part[(size_t)k * n + i];
         grad[i] = s;
     }
 }
@@ -185,7 +207,7 @@ hipError_t launch_gemm_nt(const GemmArgs& g, hipStream_t st) {
 }
 
 hipError_t launch_rowsum(const __bf16* X, int rows, int cols, int ld, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(rowsum_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, X, rows, cols, ld, out);
+    hipLaunchKernelGGL(rowsum_kernel, dim3(rows), dim3(256), 0, st, X, rows, cols, ld, out);
     return hipGetLastError();
 }
 
