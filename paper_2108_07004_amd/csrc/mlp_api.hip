@@ -155,8 +155,12 @@ int adam_all(dm_mlp* n, bool update, float lr, float b1, float b2, float eps, do
              hipStream_t st) {
     Tensor t[6];
     tensors(n, t);
-    for (auto& x : t) {
-        dm::AdamArgs a;
+    dm::AdamBatch batch;
+    std::memset(&batch, 0, sizeof batch);
+    batch.count = 6;
+    for (int k = 0; k < 6; ++k) {
+        const Tensor& x = t[k];
+        dm::AdamArgs& a = batch.t[k];
         a.w = n->w + x.off;
         a.m = n->mom + x.off;
         a.v = n->vel + x.off;
@@ -173,8 +177,9 @@ int adam_all(dm_mlp* n, bool update, float lr, float b1, float b2, float eps, do
         a.eps = eps;
         a.bc1 = (float)bc1;
         a.bc2 = (float)bc2;
-        DM_HIP_TRY(dm::launch_adam(a, st));
+        batch.start[k + 1] = batch.start[k] + (size_t)x.rows * x.cols;
     }
+    DM_HIP_TRY(dm::launch_adam_batch(batch, st));
     n->frag_dirty = true;
     return DM_OK;
 }

@@ -157,23 +157,36 @@ __global__ void reduce_splits_kernel(const float* part, int splits, size_t n, fl
 // Adam on one parameter tensor (rows x cols, row-major FP32 master), then BF16 copies:
 // copy (rows x cols row-major) and copyT (cols x rows), either may be null.  mask_rows /
 // mask_cols: entries outside [0, mask_rows) x [0, mask_cols) are padding and stay zero.
+__device__ __forceinline__ void adam_element(const AdamArgs& a, size_t i) {
+    const int rr = (int)(i / a.cols), cc = (int)(i % a.cols);
+    float w = a.w[i];
+    if (rr < a.mask_rows && cc < a.mask_cols) {
+        const float g = a.grad[i];
+        const float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
+        const float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * g * g;
+        a.m[i] = m;
+        a.v[i] = v;
+        const float mh = m / a.bc1, vh = v / a.bc2;
+        w -= a.lr * mh / (sqrtf(vh) + a.eps);
+        a.w[i] = w;
+    }
+    if (a.copy) a.copy[i] = (__bf16)w;
+    if (a.copyT) a.copyT[(size_t)cc * a.rows + rr] = (__bf16)w;
+}
+
 __global__ void adam_kernel(AdamArgs a) {
     const size_t n = (size_t)a.rows * a.cols;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        adam_element(a, i);
+}
+
+// Every tensor of a batch in one grid-stride pass (element-wise identical to adam_kernel).
+__global__ void adam_batch_kernel(AdamBatch b) {
+    const size_t n = b.start[b.count];
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int rr = (int)(i / a.cols), cc = (int)(i % a.cols);
-        float w = a.w[i];
-        if (rr < a.mask_rows && cc < a.mask_cols) {
-            const float g = a.grad[i];
-            const float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
-            const float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * g * g;
-            a.m[i] = m;
-            a.v[i] = v;
-            const float mh = m / a.bc1, vh = v / a.bc2;
-            w -= a.lr * mh / (sqrtf(vh) + a.eps);
-            a.w[i] = w;
-        }
-        if (a.copy) a.copy[i] = (__bf16)w;
-        if (a.copyT) a.copyT[(size_t)cc * a.rows + rr] = (__bf16)w;
+        int k = 0;
+        while (k + 1 < b.count && i >= b.start[k + 1]) ++k;
+        adam_element(b.t[k], i - b.start[k]);
     }
 }
 
@@ -213,6 +226,11 @@ hipError_t launch_rowsum(const __bf16* X, int rows, int cols, int ld, float* out
 
 hipError_t launch_reduce_splits(const float* part, int splits, size_t n, float* grad, hipStream_t st) {
     hipLaunchKernelGGL(reduce_splits_kernel, dim3(256), dim3(256), 0, st, part, splits, n, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_batch(const AdamBatch& b, hipStream_t st) {
+    hipLaunchKernelGGL(adam_batch_kernel, dim3(256), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

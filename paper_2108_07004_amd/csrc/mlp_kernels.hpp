@@ -55,6 +55,14 @@ hipError_t launch_gemm_nt(const GemmArgs& g, hipStream_t st);
 hipError_t launch_rowsum(const __bf16* X, int rows, int cols, int ld, float* out, hipStream_t st);
 hipError_t launch_reduce_splits(const float* part, int splits, size_t n, float* grad, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
+// Several parameter tensors in one launch: tensor k owns the flat elements [start[k], start[k+1]).
+constexpr int kAdamMaxTensors = 8;
+struct AdamBatch {
+    AdamArgs t[kAdamMaxTensors];
+    size_t start[kAdamMaxTensors + 1];
+    int count;
+};
+hipError_t launch_adam_batch(const AdamBatch& b, hipStream_t st);
 hipError_t launch_features(const float* y, const float* sigma2, int B, int D, __bf16* X, __bf16* Xt, hipStream_t st);
 
 // Number of 16-byte fragments of the inference weight table (H = 256 hidden units).
