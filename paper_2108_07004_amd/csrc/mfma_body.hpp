@@ -323,32 +323,40 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
     g = 0.0f;
     uint32_t mask = 0;
-    float* out = (b.llr && active) ? b.llr + (size_t)n * m : nullptr;
     // Lane half h finishes bits p = 2j + h: the same j for both halves keeps the control flow
-    // uniform, so every bit is processed once per wave.
+    // uniform, so every bit is processed once per wave.  The loop has no branches: a bit whose
+    // sums are out of range gets a placeholder LLR, which the fix-up overwrites, and no GMI
+    // term.  The range test runs on the bit patterns (the sums are non-negative, so unsigned
+    // order is float order, and a NaN compares above the upper bound).
+    const uint32_t lo_u = __builtin_bit_cast(uint32_t, b.flag_thresh);
+    const uint32_t hi_u = __builtin_bit_cast(uint32_t, 3.0e38f);
+    // An opaque copy of h: the lane tests below are then formed per batch (one compare each)
+    // instead of being hoisted out of the symbol loop as per-bit lane masks, which spilled.
+    int hv = h;
+    asm volatile("" : "+v"(hv));
     uint32_t flagged = 0;
+    float Lv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (2 * j < m) {
-            const int p = 2 * j + h;
+            const int p = 2 * j + hv;
+            const bool valid = p < m;  // false only in half 1 for the top bit of an odd m
             const float s0 = c0[j], s1 = c1[j];
-            if (2 * j + 1 < m || h == 0) {  // p < m, written as a uniform test or the half-0 mask
-                if (!bad_sym && fminf(s0, s1) >= b.flag_thresh && fmaxf(s0, s1) < 3.0e38f) {
-                    float gb;
-                    const float L = llr_gmi(s0, s1, (txl >> p) & 1, gb);
-                    if (out) {
-                        // The column is formed from an opaque copy of h, so that the compiler
-                        // recomputes it here instead of keeping 8 per-lane offsets live (they spilled).
-                        int hv = h;
-                        asm volatile("" : "+v"(hv));
-                        out[m - 1 - 2 * j - hv] = L * 0.69314718055994531f;
-                    }
-                    g += gb;
-                } else {
-                    flagged |= 1u << p;
-                }
-            }
+            const uint32_t u0 = __builtin_bit_cast(uint32_t, s0), u1 = __builtin_bit_cast(uint32_t, s1);
+            const bool ok = !bad_sym && min(u0, u1) >= lo_u && max(u0, u1) < hi_u;
+            float gb;
+            Lv[j] = llr_gmi(s0, s1, (txl >> p) & 1, gb) * 0.69314718055994531f;
+            g += (valid && ok) ? gb : 0.0f;
+            flagged |= (valid && !ok) ? 1u << p : 0u;
         }
+    }
+    // Stores after the loop, at constant offsets from one column pointer (bit 2j + h is
+    // column m - 1 - 2j - h), so that no store's registers are overwritten while it is in flight.
+    if (b.llr && active) {
+        float* col = b.llr + (size_t)n * m + (m - 1 - hv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (2 * j < m && 2 * j + hv < m) col[-2 * j] = Lv[j];
     }
     if (flagged) {  // rare: the GMI-only shortcut, else the exact fix-up
 #pragma unroll
