@@ -389,6 +389,89 @@ __device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint3
     }
 }
 
+// Sum / max over the 16 lanes of each row (DPP row rotations by 8, 4, 2, 1): every lane of the
+// row receives its row's result.  The whole wave must be active.
+template <typename Op>
+__device__ __forceinline__ float row_reduce_f(float v, Op op) {
+    v = op(v, dpp_f<0x128>(v));  // row_ror:8
+    v = op(v, dpp_f<0x124>(v));  // row_ror:4
+    v = op(v, dpp_f<0x122>(v));  // row_ror:2
+    v = op(v, dpp_f<0x121>(v));  // row_ror:1
+    return v;
+}
+
+// Row fix-up for a constellation of M = 16 * NPL points (M = 128 or 256, the same for every
+// queued symbol): each 16-lane row of a wavefront takes one queued symbol, so a wavefront
+// recomputes four at once.  Lane r of a row keeps the exponents t = K - c ||y - x_j||^2 of labels
+// j = r + 16 q in registers; label bits 0-3 of j are bits of r, bits 4 and up bits of q.  Each
+// flagged bit is the same two-pass subset log-sum-exp as wave_exact_llr2 (subset maxima, then
+// the exp2 sums under them), reduced over the row.  Lane 0 of the row writes the LLR and
+// accumulates the GMI / MI corrections, which add(tag, slot, which, value) receives.
+template <int DP, int NPL, typename ViewFn, typename AddFn>
+__device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count) {
+    constexpr int m = NPL == 8 ? 7 : 8;
+    static_assert(NPL == 8 || NPL == 16, "row fix-up covers M = 128 and 256");
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const int slot = (int)(wave % kAccSlots);
+    const auto fmax2 = [](float a, float b) { return fmaxf(a, b); };
+    const auto fadd2 = [](float a, float b) { return a + b; };
+    for (uint32_t base = wave * 4; base < count; base += nwaves * 4) {  // uniform over the wave
+        const uint32_t i = base + (uint32_t)(lane >> 4);
+        const bool live = i < count;
+        const FixEntry e = k.queue[live ? i : base];  // a spare row repeats a valid entry, masked off
+        const uint32_t mask = live ? e.mask : 0u;
+        const BlockView b = view(e);
+        float y[DP];
+        load_symbol<DP>(y, b.y + (size_t)e.n * b.D, b.D, true);
+        const int txl = b.tx ? tx_label(b, k, e.n) : 0;
+        float t[NPL];
+#pragma unroll
+        for (int q = 0; q < NPL; ++q) t[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K);
+        double gc = 0.0, mc = 0.0;
+        // p = 0 .. m-1: label bits; p = m: the MI term (every point in subset 0).
+        for (int p = 0; p <= m; ++p) {
+            const bool want = p < m ? ((mask >> p) & 1u) != 0u : ((mask & kMiFlag) != 0u && b.tx != nullptr);
+            if (__ballot(want) == 0ull) continue;
+            float mx0 = -INFINITY, mx1 = -INFINITY;
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) {
+                const bool one = p < 4 ? ((r >> p) & 1) != 0 : (p < m && ((q >> (p - 4)) & 1) != 0);
+                if (one) mx1 = fmaxf(mx1, t[q]);
+                else mx0 = fmaxf(mx0, t[q]);
+            }
+            mx0 = row_reduce_f(mx0, fmax2);
+            mx1 = row_reduce_f(mx1, fmax2);
+            float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) {
+                const bool one = p < 4 ? ((r >> p) & 1) != 0 : (p < m && ((q >> (p - 4)) & 1) != 0);
+                if (one) s1 += hw_exp2(t[q] - mx1);
+                else s0 += hw_exp2(t[q] - mx0);
+            }
+            s0 = row_reduce_f(s0, fadd2);
+            s1 = row_reduce_f(s1, fadd2);
+            if (want && r == 0) {
+                if (p < m) {
+                    const float L = (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
+                    if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
+                    if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
+                } else {
+                    const float lse_all = mx0 + hw_log2(s0);
+                    const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
+                    mc += (double)((float)m - (lse_all - ttx));
+                }
+            }
+        }
+        if (live && r == 0) {
+            add((int)e.tag, slot, 0, gc);
+            add((int)e.tag, slot, 1, mc);
+        }
+    }
+}
+
 // Drain the fix-up queue: symbols of constellations with at most kFixLaneMaxM points are
 // recomputed one per lane (fixup_one: cheaper than wave reductions for so few points), the
 // others one per wavefront (fixup_wave).  view(e) gives the block of a queue entry; tl is the
@@ -397,7 +480,7 @@ __device__ void fixup_wave(const BlockView& b, const Sinks& k, uint32_t n, uint3
 constexpr int kFixLaneMaxM = 64;
 
 template <int DP, typename ViewFn>
-__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cache_pts) {
+__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cache_pts, int uniform_M = 0) {
     // Corrections of blocks (tags) below kFixLdsTags are summed per workgroup in LDS, as the same
     // fixed-point integers acc_add uses (so the totals are unchanged and order-independent), and
     // flushed once per workgroup: per-entry global atomics were the fix-up's bottleneck.
@@ -414,10 +497,15 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
             acc_add(k.acc, tag, slot, which, v);
         }
     };
-    const uint32_t count = min(*k.queue_count, k.queue_cap);
+    uint32_t count = min(*k.queue_count, k.queue_cap);
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    if (uniform_M == 128 || uniform_M == 256) {  // every entry has that M: four symbols per wave
+        if (uniform_M == 128) fix_rows<DP, 8>(k, view, add, count);
+        else fix_rows<DP, 16>(k, view, add, count);
+        count = 0;  // nothing left for the lane and wave passes
+    }
     for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
         const uint32_t i = base + lane;
         if (i < count) {
