@@ -77,7 +77,10 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
 
         MfmaAcc A;
         A.init();
-        for (int ch = 0; ch < nchunks; ++ch) {
+        // At least one chunk (M >= 32): a do-while leaves no zero-trip path, on which the
+        // compiler would materialise the accumulators' zeros a second time every batch.
+        int ch = 0;
+        do {
             const int t0 = ch * chunk_tiles;
             const int cnt = min(chunk_tiles, ntiles - t0);
             if (nchunks > 1) {
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
                 __syncthreads();
             }
             mfma_tiles<T, D, SPLIT>(lds_frag, lane, t0, cnt, b.m, bfr, A);
-        }
+        } while (++ch < nchunks);
         float g, mi;
         mfma_epilogue<T, D, SPLIT>(b, k, pv, bfr, A, n, active, bad, lane, g, mi);
         if (k.acc && active) {
