@@ -81,10 +81,11 @@ __global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs
                 load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
                 bool bad = false;
                 const Frags<T, S> bfr = build_symbol_frags<T, 8, SPLIT>(y, b.c, b.K, h, bad);
+                const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
                 MfmaAcc A;
                 A.init();
                 mfma_tiles<T, 8, SPLIT>(lds_raw, lane, 0, b.M >> 5, b.m, bfr, A);
-                mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, lane, g, mi);
+                mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, txl, lane, g, mi);
             } else {
                 const int64_t n = it.n0 + tid;
                 active = n < b.N;

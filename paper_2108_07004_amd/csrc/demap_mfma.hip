@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
         bool bad = false;
         const Frags<T, S> bfr = build_symbol_frags<T, D, SPLIT>(y, b.c, b.K, h, bad);
 
+        const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
         MfmaAcc A;
         A.init();
         // At least one chunk (M >= 32): a do-while leaves no zero-trip path, on which the
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(kMfmaThreads) void demap_mfma_kernel(const LaunchAr
             mfma_tiles<T, D, SPLIT>(lds_frag, lane, t0, cnt, b.m, bfr, A);
         } while (++ch < nchunks);
         float g, mi;
-        mfma_epilogue<T, D, SPLIT>(b, k, pv, bfr, A, n, active, bad, lane, g, mi);
+        mfma_epilogue<T, D, SPLIT>(b, k, pv, bfr, A, n, active, bad, txl, lane, g, mi);
         if (k.acc && active) {
             gsum += (double)g;
             msum += (double)mi;

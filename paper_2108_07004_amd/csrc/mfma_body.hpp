@@ -259,11 +259,13 @@ __device__ __forceinline__ void mfma_tiles(const uint4* lds_frag, int lane, int 
 }
 
 // Combine the two lanes of each symbol, write LLRs, flag and queue underflowed bits and form
-// the per-symbol GMI (both halves) and MI (half 0) terms.
+// the per-symbol GMI (both halves) and MI (half 0) terms.  txl is the symbol's transmitted label
+// (0 without tx), loaded by the caller before the tile loop so that its latency is hidden.
 template <typename T, int D, bool SPLIT>
 __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k, const uint16_t* pv,
                                               const Frags<T, Slots<D, SPLIT>::S>& bfr, const MfmaAcc& A,
-                                              int64_t n, bool active, bool bad, int lane, float& g, float& mi) {
+                                              int64_t n, bool active, bool bad, int txl, int lane, float& g,
+                                              float& mi) {
     using V = typename Mma<T>::V;
     constexpr int S = Slots<D, SPLIT>::S;
     const int h = lane >> 5;
@@ -320,7 +322,6 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     const bool bad_sym = half_or((uint32_t)bad) != 0;
     const float stot = half_pair_sum(tot, tot);
 
-    const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
     g = 0.0f;
     uint32_t mask = 0;
     // Lane half h finishes bits p = 2j + h: the same j for both halves keeps the control flow
