@@ -41,10 +41,10 @@ EXP2_ISSUE_CYCLES = 2  # v_exp_f32 issues at half the full FP32 rate on gfx950 (
 # 512 MiB device copy in the same runs.  Valid only for the kernel sources they were taken on.
 TRAFFIC_PMC = {
     "prec": "fp16x3", "workload": "gauss8d2048",
-    "bytes": (4475512 * 2 + 11546674) * 1024,
+    "bytes": (4482193 * 2 + 11546636) * 1024,
     "sources": ["paper_2108_07004_amd/csrc/demap_mfma.hip", "paper_2108_07004_amd/csrc/mfma_body.hpp",
                 "paper_2108_07004_amd/csrc/device_common.hpp"],
-    "sha256": "74962c6d242a4fca8406233b64ec947bb6331168375bf2e8b59b4d64eaa369cb",
+    "sha256": "a3fa1e593ea1d99b65845df89676ee3f3cfb630f5442cdd63663f0adeb15f717",
 }
 
 
