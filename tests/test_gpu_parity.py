@@ -174,3 +174,29 @@ def _sampled_full_size(name, snr_idx, prec, tol, n_runs=8, run_len=48):
 
 def test_dp16qam_full_size_sampled():
     _sampled_full_size("dp16qam", [0, 5, 10], "fp32", LLR_TOL_FP32)
+
+
+@pytest.mark.parametrize("name", ["dp16qam", "128qam"])
+def test_row_fixup_with_per_symbol_variance(name):
+    # M = 256 and 128 send their underflowed bits to the fix-up's 16-lane rows (four symbols per
+    # wavefront); per-symbol variances at 12..26 dB make most symbols' far subsets underflow, and
+    # N = 3001 leaves a partial last group of rows.
+    import torch
+    c = W.dp_16qam() if name == "dp16qam" else W.qam(128)
+    const = dm.Constellation(c.points, c.labels)
+    N = 3001
+    g = W.rng(9, "misc", c.M)
+    levels = np.array([12.0, 18.0, 22.0, 26.0])
+    pick = g.integers(0, len(levels), N)
+    s2 = W.sigma2_from_snr_db(levels)[pick].astype(np.float32)
+    tx = g.integers(0, c.M, N).astype(np.uint16)
+    z = g.standard_normal((N, c.D))
+    y = (c.points.astype(np.float64)[tx] + np.sqrt(s2.astype(np.float64))[:, None] * z).astype(np.float32)
+    dev = torch.device("cuda:0")
+    got = dm.demap_llr_var(const, torch.from_numpy(s2).to(dev), torch.from_numpy(y).to(dev)).cpu().numpy()
+    for k in range(len(levels)):
+        idx = np.nonzero(pick == k)[0]
+        ref = oracle.demap(c.points, c.labels, float(s2[idx[0]]), y[idx], tx[idx])
+        e = rel_err(got[idx], ref["llr"])
+        print(f"{name} {levels[k]:.0f} dB: {len(idx)} symbols, LLR rel err {e:.2e}", flush=True)
+        assert e <= LLR_TOL_FP32, (name, levels[k], e)
