@@ -127,9 +127,11 @@ typedef struct dm_plan dm_plan;
 
 /*
  * Build a plan for n_inst instances (copied; their device buffers must stay valid for the
- * plan's lifetime): autotune if asked, split the work list into one cost-balanced contiguous
- * segment per compute unit, allocate all scratch and capture zero-fill + batched kernel +
- * fix-up into a hipGraph.  Synchronous (runs timing launches when autotuning).
+ * plan's lifetime): autotune if asked, list the work items (symbol tiles of each instance, the
+ * most costly instance first), allocate all scratch and capture zero-fill + batched kernel +
+ * fix-up into a hipGraph.  At run time each workgroup claims the next chunk of work items from
+ * a device counter until the list is exhausted (dynamic balance).  Synchronous (runs timing
+ * launches when autotuning).
  * Errors: DM_EINVAL, DM_EUNSUPPORTED, DM_EHIP, DM_ENOMEM.
  */
 int dm_plan_create(const dm_instance* inst, int n_inst, int prec, int flags, dm_plan** out);
@@ -143,6 +145,10 @@ int dm_plan_results(dm_plan* plan, double* gmi, double* mi, int64_t* fixup_pairs
 
 /* Per-instance kernel body chosen (0 = FP32, 1 = MFMA) and its cost in ns per (symbol, point). */
 int dm_plan_info(const dm_plan* plan, int* kinds, double* ns_per_pair);
+
+/* Launch shape of a plan (any output may be NULL): work items in its list, items a workgroup
+ * claims at a time, and workgroups of the persistent launch. */
+int dm_plan_stats(const dm_plan* plan, int64_t* n_items, int32_t* claim_items, int32_t* grid);
 
 void dm_plan_destroy(dm_plan* plan);
 
@@ -163,8 +169,9 @@ int dm_demap_llr_var(const dm_constellation* c, const float* sigma2, const float
                      int prec, void* stream);
 
 /* ------------------------------------------------------------------------------------------
- * Learned demapper.  The paper replaces nothing by a network; it names learned (neural-
- * network) demapping among the receiver's future directions (Sec. 6).  The network here is an
+ * Learned demapper.  This is a project addition with no passage in the paper: the paper's
+ * receiver demaps by minimum distance (Sec. 2) and mentions no learned demapping.  The network
+ * judged by the exact path of this library (its fallback and its GMI-loss audit) is an
  * MLP (D+1) -> 256 -> 256 -> m with tanh-form GELU, BF16 weights and activations and FP32
  * accumulation, whose m outputs estimate the exact LLRs (nats).  Its inputs are y and the SNR
  * feature (s - 7.5) / 7.5 with s = -10 log10(2 sigma2), the SNR in dB of a constellation with

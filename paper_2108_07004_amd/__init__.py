@@ -70,6 +70,8 @@ def load_library():
     lib.dm_plan_results.restype = I
     lib.dm_plan_info.argtypes = [P, P, P]
     lib.dm_plan_info.restype = I
+    lib.dm_plan_stats.argtypes = [P, P, P, P]
+    lib.dm_plan_stats.restype = I
     lib.dm_plan_destroy.argtypes = [P]
     lib.dm_plan_destroy.restype = None
     lib.dm_demap_batched.argtypes = [P, I, I, I, P, P, P]
@@ -159,6 +161,17 @@ class Constellation:
     @property
     def handle(self):
         return self._h
+
+    def stats(self):
+        """(work items, items per claim, workgroups) of the plan's launch."""
+        n = ctypes.c_int64()
+        grab = ctypes.c_int32()
+        grid = ctypes.c_int32()
+        _check(load_library().dm_plan_stats(self._h, ctypes.byref(n), ctypes.byref(grab), ctypes.byref(grid)))
+        return int(n.value), int(grab.value), int(grid.value)
+
+    def work_items(self):
+        return self.stats()[0]
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -306,6 +319,17 @@ class Plan:
         _check(load_library().dm_plan_info(self._h, kinds.ctypes.data_as(ctypes.c_void_p),
                                            ns.ctypes.data_as(ctypes.c_void_p)))
         return kinds, ns
+
+    def stats(self):
+        """(work items, items per claim, workgroups) of the plan's launch."""
+        n = ctypes.c_int64()
+        grab = ctypes.c_int32()
+        grid = ctypes.c_int32()
+        _check(load_library().dm_plan_stats(self._h, ctypes.byref(n), ctypes.byref(grab), ctypes.byref(grid)))
+        return int(n.value), int(grab.value), int(grid.value)
+
+    def work_items(self):
+        return self.stats()[0]
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -460,6 +484,17 @@ class MLP:
                                                ctypes.byref(loss), _stream_handle(stream)))
         return _unflatten(flat, self.D, self.m), loss.value
 
+    def stats(self):
+        """(work items, items per claim, workgroups) of the plan's launch."""
+        n = ctypes.c_int64()
+        grab = ctypes.c_int32()
+        grid = ctypes.c_int32()
+        _check(load_library().dm_plan_stats(self._h, ctypes.byref(n), ctypes.byref(grab), ctypes.byref(grid)))
+        return int(n.value), int(grab.value), int(grid.value)
+
+    def work_items(self):
+        return self.stats()[0]
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             load_library().dm_mlp_destroy(self._h)
@@ -606,6 +641,17 @@ class Streamer:
         _check(load_library().dm_streamer_run(self._h, float(sigma2), y.ctypes.data_as(ctypes.c_void_p), N,
                                               llr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sec)))
         return llr, sec.value
+
+    def stats(self):
+        """(work items, items per claim, workgroups) of the plan's launch."""
+        n = ctypes.c_int64()
+        grab = ctypes.c_int32()
+        grid = ctypes.c_int32()
+        _check(load_library().dm_plan_stats(self._h, ctypes.byref(n), ctypes.byref(grab), ctypes.byref(grid)))
+        return int(n.value), int(grab.value), int(grid.value)
+
+    def work_items(self):
+        return self.stats()[0]
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -1,6 +1,6 @@
 // Batched demapping plans: one persistent launch over many instances of uneven M, D and N,
-// an autotuner that picks the kernel body per (M, D, precision) class by timing, a
-// cost-balanced contiguous split of the work list over the workgroups, and a hipGraph that
+// an autotuner that picks the kernel body per (M, D, precision) class by timing, a work list
+// that workgroups claim chunk by chunk from a device counter at run time, and a hipGraph that
 // replays zero-fill + batched kernel + fix-up with one launch.
 #include <hip/hip_runtime.h>
 
@@ -422,6 +422,14 @@ int dm_plan_info(const dm_plan* p, int* kinds, double* ns_per_pair) {
         if (kinds) kinds[i] = p->kind[i];
         if (ns_per_pair) ns_per_pair[i] = p->ns_per_pair[i];
     }
+    return DM_OK;
+}
+
+int dm_plan_stats(const dm_plan* p, int64_t* n_items, int32_t* claim_items, int32_t* grid) {
+    if (!p) return fail(DM_EINVAL, "null plan");
+    if (n_items) *n_items = p->args.n_items;
+    if (claim_items) *claim_items = p->args.grab;
+    if (grid) *grid = p->grid;
     return DM_OK;
 }
 
