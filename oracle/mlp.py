@@ -104,6 +104,15 @@ def bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def bf16x2_round(x):
+    """A value carried as two BF16 words: hi = bf16(x), lo = bf16(x - hi) (the difference taken
+    in FP32), returned as hi + lo in float64 (about 16 significant bits)."""
+    x32 = np.asarray(x, dtype=np.float64).astype(np.float32)
+    hi = bf16_round(x32)
+    lo = bf16_round((x32 - hi.astype(np.float32)).astype(np.float32))
+    return hi + lo
+
+
 def identity(x):
     return np.asarray(x, dtype=np.float64)
 

@@ -130,3 +130,70 @@ def test_stored_rounding_hooks_reduce_to_the_pinned_network():
     # with BF16 storage the result moves by about the BF16 resolution, not more
     out3, _ = mlp.forward_stored(w, X)
     assert 0 < np.max(np.abs(out3 - out)) < 0.05 * np.max(np.abs(out))
+
+
+def _torch_net(w, X, T):
+    """The same network and loss written with torch's own library routines (float64, CPU):
+    torch.nn.functional.gelu(approximate="tanh"), matmul, binary_cross_entropy_with_logits."""
+    import torch
+    import torch.nn.functional as F
+    tw = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in w.items()}
+    x = torch.tensor(X, dtype=torch.float64)
+    t = torch.tensor(T, dtype=torch.float64)
+    a1 = F.gelu(x @ tw["W1"] + tw["b1"], approximate="tanh")
+    a2 = F.gelu(a1 @ tw["W2"] + tw["b2"], approximate="tanh")
+    out = a2 @ tw["W3"] + tw["b3"]
+    p = torch.sigmoid(t)
+    # soft BCE minus its minimum (the entropy of p), averaged over samples and bits
+    loss = (F.binary_cross_entropy_with_logits(out, p, reduction="none")
+            - F.binary_cross_entropy_with_logits(t, p, reduction="none")).mean()
+    loss.backward()
+    return out.detach().numpy(), loss.item(), {k: v.grad.numpy() for k, v in tw.items()}
+
+
+def test_forward_loss_and_gradients_match_torch_library_routines():
+    w, X, T = _tiny(seed=8, D=3, H=6, m=4, B=9)
+    out, cache = mlp.forward(w, X)
+    t_out, t_loss, t_grad = _torch_net(w, X, T)
+    assert np.max(np.abs(out - t_out)) <= 1e-13 * max(1.0, np.max(np.abs(t_out)))
+    assert abs(mlp.loss(out, T) - t_loss) <= 1e-14 * max(1.0, abs(t_loss))
+    g = mlp.backward(w, cache, out, T)
+    for k in w:
+        assert np.max(np.abs(g[k] - t_grad[k])) <= 1e-13 * max(1e-3, np.max(np.abs(t_grad[k]))), k
+
+
+def test_gelu_tanh_form_known_value():
+    # the tanh-form GELU at 1 (as torch's approximate="tanh" gives it): 0.8411919906082768
+    assert abs(mlp.gelu(np.array([1.0]))[0] - 0.8411919906082768) <= 1e-15
+    assert abs(mlp.gelu(np.array([-1.0]))[0] + 0.15880800939172324) <= 1e-15
+
+
+def test_adam_several_steps_match_torch_optimizer():
+    import torch
+    w, X, T = _tiny(seed=13)
+    state = {}
+    tw = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in w.items()}
+    opt = torch.optim.Adam(list(tw.values()), lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    g = np.random.default_rng(21)
+    for step in range(1, 6):  # bias corrections beyond the first step
+        grads = {k: g.normal(0, 1e-2 * step, v.shape) for k, v in w.items()}
+        mlp.adam_step(w, grads, state, lr=3e-3, step=step)
+        opt.zero_grad()
+        for k, v in tw.items():
+            v.grad = torch.tensor(grads[k], dtype=torch.float64)
+        opt.step()
+        for k in w:
+            assert np.max(np.abs(w[k] - tw[k].detach().numpy())) <= 1e-15, (step, k)
+
+
+def test_bf16_hi_lo_pair_known_values():
+    # x = 1 + 2^-8 + 2^-12: hi rounds up to 1 + 2^-7, x - hi = -15 * 2^-12 is a BF16 value, so the
+    # pair represents x exactly while one BF16 word is off by 15 * 2^-12
+    x = np.array([1.0 + 2.0 ** -8 + 2.0 ** -12])
+    assert mlp.bf16_round(x)[0] == 1.0 + 2.0 ** -7
+    assert mlp.bf16x2_round(x)[0] == x[0]
+    # in general the pair keeps about 16 significant bits
+    v = np.random.default_rng(1).normal(0, 3, 4000).astype(np.float32).astype(np.float64)
+    r = mlp.bf16x2_round(v)
+    assert np.all(np.abs(r - v) <= np.abs(v) * 2.0 ** -16)
+    assert np.max(np.abs(r - v) / np.abs(v)) > 2.0 ** -20  # and not all 24
