@@ -62,6 +62,10 @@ struct dm_mlp {
     int B = 0;
     __bf16 *X = nullptr, *Xt = nullptr, *A1 = nullptr, *A1T = nullptr, *A2 = nullptr, *A2T = nullptr;
     __bf16 *dO = nullptr, *dOT = nullptr, *dH2 = nullptr, *dH2T = nullptr, *dH1T = nullptr;
+    // Activations and deltas are BF16 pairs: each allocation above except X / Xt holds the hi
+    // words, then the lo words (these pointers, into the same allocations).
+    __bf16 *A1lo = nullptr, *A1Tlo = nullptr, *A2lo = nullptr, *A2Tlo = nullptr, *dOlo = nullptr, *dOTlo = nullptr;
+    __bf16 *dH2lo = nullptr, *dH2Tlo = nullptr, *dH1Tlo = nullptr;
     float *H1 = nullptr, *H2 = nullptr, *part = nullptr, *loss_hist = nullptr;
     size_t part_floats = 0;
     float* targets = nullptr;
@@ -188,14 +192,24 @@ int ensure_batch(dm_mlp* n, int B) {
     if (n->B >= B) return DM_OK;
     const size_t b = (size_t)B;
     int r;
+    n->B = 0;
     if ((r = dev_alloc(n->X, b * 16, "X")) || (r = dev_alloc(n->Xt, 32 * b, "Xt")) ||
-        (r = dev_alloc(n->A1, b * kH, "A1")) || (r = dev_alloc(n->A1T, b * kH, "A1T")) ||
-        (r = dev_alloc(n->A2, b * kH, "A2")) || (r = dev_alloc(n->A2T, b * kH, "A2T")) ||
-        (r = dev_alloc(n->dO, b * 32, "dO")) || (r = dev_alloc(n->dOT, b * 32, "dOT")) ||
-        (r = dev_alloc(n->dH2, b * kH, "dH2")) || (r = dev_alloc(n->dH2T, b * kH, "dH2T")) ||
-        (r = dev_alloc(n->dH1T, b * kH, "dH1T")) || (r = dev_alloc(n->H1, b * kH, "H1")) ||
+        (r = dev_alloc(n->A1, 2 * b * kH, "A1")) || (r = dev_alloc(n->A1T, 2 * b * kH, "A1T")) ||
+        (r = dev_alloc(n->A2, 2 * b * kH, "A2")) || (r = dev_alloc(n->A2T, 2 * b * kH, "A2T")) ||
+        (r = dev_alloc(n->dO, 2 * b * 32, "dO")) || (r = dev_alloc(n->dOT, 2 * b * 32, "dOT")) ||
+        (r = dev_alloc(n->dH2, 2 * b * kH, "dH2")) || (r = dev_alloc(n->dH2T, 2 * b * kH, "dH2T")) ||
+        (r = dev_alloc(n->dH1T, 2 * b * kH, "dH1T")) || (r = dev_alloc(n->H1, b * kH, "H1")) ||
         (r = dev_alloc(n->H2, b * kH, "H2")) || (r = dev_alloc(n->loss_hist, (size_t)kLossHist * (b / 32), "loss")))
         return r;
+    n->A1lo = n->A1 + b * kH;
+    n->A1Tlo = n->A1T + b * kH;
+    n->A2lo = n->A2 + b * kH;
+    n->A2Tlo = n->A2T + b * kH;
+    n->dOlo = n->dO + b * 32;
+    n->dOTlo = n->dOT + b * 32;
+    n->dH2lo = n->dH2 + b * kH;
+    n->dH2Tlo = n->dH2T + b * kH;
+    n->dH1Tlo = n->dH1T + b * kH;
     n->part_floats = std::max<size_t>(16 * 65536, 64 * 8192);
     if ((r = dev_alloc(n->part, n->part_floats, "split-K partials"))) return r;
     n->B = B;
@@ -224,9 +238,13 @@ dm::GemmArgs gemm(const __bf16* A, int lda, const __bf16* Bt, int ldb, int M, in
     return g;
 }
 
-// Weight gradient C[M x N] = A[M x B] . Bt[N x B]^T, split over B, reduced into grad + off.
-int weight_grad(dm_mlp* n, const __bf16* A, const __bf16* Bt, int M, int N, int B, int cap, size_t off, hipStream_t st) {
+// Weight gradient C[M x N] = A[M x B] . Bt[N x B]^T (each operand with its optional low words),
+// split over B, reduced into grad + off.
+int weight_grad(dm_mlp* n, const __bf16* A, const __bf16* A_lo, const __bf16* Bt, const __bf16* Bt_lo, int M, int N,
+                int B, int cap, size_t off, hipStream_t st) {
     dm::GemmArgs g = gemm(A, B, Bt, B, M, N, B, dm::kEpiPartial);
+    g.A_lo = A_lo;
+    g.Bt_lo = Bt_lo;
     g.splits = k_splits(B, cap);
     g.part = n->part;
     DM_HIP_TRY(dm::launch_gemm_nt(g, st));
@@ -244,56 +262,69 @@ int enqueue_grad(dm_mlp* n, int B, const float* y, const float* sigma2, const fl
     g.Hout = n->H1;
     g.ldh = kH;
     g.Aout = n->A1;
+    g.Aout_lo = n->A1lo;
     g.ldo = kH;
     g.AoutT = n->A1T;
+    g.AoutT_lo = n->A1Tlo;
     g.ldt = B;
     DM_HIP_TRY(dm::launch_gemm_nt(g, st));
     // layer 2
     g = gemm(n->A1, kH, n->W2t, kH, B, kH, kH, dm::kEpiFwdHidden);
+    g.A_lo = n->A1lo;
     g.bias = n->w + oB2;
     g.Hout = n->H2;
     g.ldh = kH;
     g.Aout = n->A2;
+    g.Aout_lo = n->A2lo;
     g.ldo = kH;
     g.AoutT = n->A2T;
+    g.AoutT_lo = n->A2Tlo;
     g.ldt = B;
     DM_HIP_TRY(dm::launch_gemm_nt(g, st));
     // layer 3 + loss + output gradient
     g = gemm(n->A2, kH, n->W3t, kH, B, 32, kH, dm::kEpiFwdOut);
+    g.A_lo = n->A2lo;
     g.bias = n->w + oB3;
     g.target = target;
     g.ld_target = n->m;
     g.mout = n->m;
     g.scale = (float)(1.0 / ((double)B * n->m));
     g.Aout = n->dO;
+    g.Aout_lo = n->dOlo;
     g.ldo = 32;
     g.AoutT = n->dOT;
+    g.AoutT_lo = n->dOTlo;
     g.ldt = B;
     g.loss_tiles = loss_tiles;
     DM_HIP_TRY(dm::launch_gemm_nt(g, st));
     int r;
-    if ((r = weight_grad(n, n->dOT, n->A2T, 32, kH, B, 64, oW3, st))) return r;
-    DM_HIP_TRY(dm::launch_rowsum(n->dOT, 32, B, B, n->grad + oB3, st));
+    if ((r = weight_grad(n, n->dOT, n->dOTlo, n->A2T, n->A2Tlo, 32, kH, B, 64, oW3, st))) return r;
+    DM_HIP_TRY(dm::launch_rowsum(n->dOT, n->dOTlo, 32, B, B, n->grad + oB3, st));
     // back through layer 3 and GELU 2
     g = gemm(n->dO, 32, n->W3, 32, B, kH, 32, dm::kEpiBwdHidden);
+    g.A_lo = n->dOlo;
     g.Hin = n->H2;
     g.ldh = kH;
     g.Aout = n->dH2;
+    g.Aout_lo = n->dH2lo;
     g.ldo = kH;
     g.AoutT = n->dH2T;
+    g.AoutT_lo = n->dH2Tlo;
     g.ldt = B;
     DM_HIP_TRY(dm::launch_gemm_nt(g, st));
-    if ((r = weight_grad(n, n->dH2T, n->A1T, kH, kH, B, 16, oW2, st))) return r;
-    DM_HIP_TRY(dm::launch_rowsum(n->dH2T, kH, B, B, n->grad + oB2, st));
+    if ((r = weight_grad(n, n->dH2T, n->dH2Tlo, n->A1T, n->A1Tlo, kH, kH, B, 16, oW2, st))) return r;
+    DM_HIP_TRY(dm::launch_rowsum(n->dH2T, n->dH2Tlo, kH, B, B, n->grad + oB2, st));
     // back through layer 2 and GELU 1
     g = gemm(n->dH2, kH, n->W2, kH, B, kH, kH, dm::kEpiBwdHidden);
+    g.A_lo = n->dH2lo;
     g.Hin = n->H1;
     g.ldh = kH;
     g.AoutT = n->dH1T;
+    g.AoutT_lo = n->dH1Tlo;
     g.ldt = B;
     DM_HIP_TRY(dm::launch_gemm_nt(g, st));
-    if ((r = weight_grad(n, n->dH1T, n->Xt, kH, 32, B, 64, oW1, st))) return r;
-    DM_HIP_TRY(dm::launch_rowsum(n->dH1T, kH, B, B, n->grad + oB1, st));
+    if ((r = weight_grad(n, n->dH1T, n->dH1Tlo, n->Xt, nullptr, kH, 32, B, 64, oW1, st))) return r;
+    DM_HIP_TRY(dm::launch_rowsum(n->dH1T, n->dH1Tlo, kH, B, B, n->grad + oB1, st));
     return DM_OK;
 }
 

@@ -5,12 +5,19 @@
 // K-contiguous (row-major A, row-major Bt), one wavefront per 32 x 32 output tile and an
 // optional split of K, followed by a fused epilogue:
 //   PARTIAL      FP32 partial sums part[split][M][N] (weight gradients over the batch);
-//   FWD_HIDDEN   h = acc + b; H = h (FP32); a = gelu(h) stored as BF16 row-major and transposed;
-//   FWD_OUT      o = acc + b; dO = (sigmoid(o) - sigmoid(t)) / (B m) as BF16 row-major and
+//   FWD_HIDDEN   h = acc + b; H = h (FP32); a = gelu(h) stored row-major and transposed;
+//   FWD_OUT      o = acc + b; dO = (sigmoid(o) - sigmoid(t)) / (B m) stored row-major and
 //                transposed, and the soft-BCE loss summed per tile;
-//   BWD_HIDDEN   dh = acc * gelu'(H) stored as BF16 row-major and transposed.
+//   BWD_HIDDEN   dh = acc * gelu'(H) stored row-major and transposed.
 // Gradients are then reduced over the K splits in a fixed order (deterministic) and Adam
 // updates the FP32 master weights and rewrites their BF16 copies.
+//
+// Activations and back-propagated deltas are stored as BF16 pairs hi + lo (lo = the rounding
+// remainder, about 16 significant bits together) and enter every product that reads them as
+// such: hi.b + lo.b, or hi.hi + hi.lo + lo.hi when both operands are pairs.  Only the weights
+// (BF16 copies of the FP32 masters) and the network inputs are single BF16 words, so the
+// gradients are those of the network on BF16-rounded weights and inputs, with activations and
+// deltas carried to about 2^-16 relative instead of BF16's 2^-8.
 #include <hip/hip_runtime.h>
 
 #include "mlp_kernels.hpp"
@@ -44,6 +51,15 @@ __device__ __forceinline__ float softplus_f(float x) {
     return fmaxf(x, 0.0f) + 0.69314718055994531f * __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * fabsf(x)));
 }
 
+// Stores v as a BF16 pair: hi[idx] = bf16(v), lo[idx] = bf16(v - hi) (the difference is exact
+// in FP32); lo may be null.
+__device__ __forceinline__ void store_pair(__bf16* hi, __bf16* lo, size_t idx, float v) {
+    const __bf16 h = (__bf16)v;
+    hi[idx] = h;
+    if (lo) lo[idx] = (__bf16)(v - (float)h);
+}
+
+template <bool ALO, bool BLO>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -56,12 +72,20 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
     const int kc = g.K / g.splits;
     const int k_begin = split * kc, k_end = k_begin + kc;
     const int r = lane & 31, h = lane >> 5;
-    const __bf16* ap = g.A + (size_t)(m0 + r) * g.lda + 8 * h;
-    const __bf16* bp = g.Bt + (size_t)(n0 + r) * g.ldb + 8 * h;
+    const size_t aoff = (size_t)(m0 + r) * g.lda + 8 * h;
+    const size_t boff = (size_t)(n0 + r) * g.ldb + 8 * h;
     f32x16 acc = {};
     for (int k = k_begin; k < k_end; k += 16) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap + k);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(bp + k);
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(g.A + aoff + k);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(g.Bt + boff + k);
+        if constexpr (ALO) {
+            const bf16x8 al = *reinterpret_cast<const bf16x8*>(g.A_lo + aoff + k);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, b, acc, 0, 0, 0);
+        }
+        if constexpr (BLO) {
+            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(g.Bt_lo + boff + k);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bl, acc, 0, 0, 0);
+        }
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     const int j = n0 + r;  // output column of this lane
@@ -77,29 +101,29 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
             case kEpiFwdHidden: {
                 const float hv = v + g.bias[j];
                 g.Hout[(size_t)i * g.ldh + j] = hv;
-                const __bf16 a = (__bf16)gelu_f(hv);
-                g.Aout[(size_t)i * g.ldo + j] = a;
-                g.AoutT[(size_t)j * g.ldt + i] = a;
+                const float a = gelu_f(hv);
+                store_pair(g.Aout, g.Aout_lo, (size_t)i * g.ldo + j, a);
+                store_pair(g.AoutT, g.AoutT_lo, (size_t)j * g.ldt + i, a);
                 break;
             }
             case kEpiFwdOut: {
-                __bf16 d = (__bf16)0.0f;
+                float d = 0.0f;
                 if (j < g.mout) {
                     const float o = v + g.bias[j];
                     const float t = g.target[(size_t)i * g.ld_target + j];
                     const float p = sigmoid_f(t);
-                    d = (__bf16)((sigmoid_f(o) - p) * g.scale);
+                    d = (sigmoid_f(o) - p) * g.scale;
                     loss += (softplus_f(o) - p * o) - (softplus_f(t) - p * t);
                     if (g.Hout) g.Hout[(size_t)i * g.ldh + j] = o;
                 }
-                g.Aout[(size_t)i * g.ldo + j] = d;
-                g.AoutT[(size_t)j * g.ldt + i] = d;
+                store_pair(g.Aout, g.Aout_lo, (size_t)i * g.ldo + j, d);
+                store_pair(g.AoutT, g.AoutT_lo, (size_t)j * g.ldt + i, d);
                 break;
             }
             case kEpiBwdHidden: {
-                const __bf16 d = (__bf16)(v * gelu_grad_f(g.Hin[(size_t)i * g.ldh + j]));
-                if (g.Aout) g.Aout[(size_t)i * g.ldo + j] = d;
-                g.AoutT[(size_t)j * g.ldt + i] = d;
+                const float d = v * gelu_grad_f(g.Hin[(size_t)i * g.ldh + j]);
+                if (g.Aout) store_pair(g.Aout, g.Aout_lo, (size_t)i * g.ldo + j, d);
+                store_pair(g.AoutT, g.AoutT_lo, (size_t)j * g.ldt + i, d);
                 break;
             }
         }
@@ -111,23 +135,31 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
     }
 }
 
-// Row sums of a BF16 matrix (rows contiguous): out[row] = sum_b X[row][b].
-__global__ __launch_bounds__(256) void rowsum_kernel(const __bf16* X, int rows, int cols, int ld, float* out) {
+// Row sums of a BF16 matrix (rows contiguous): out[row] = sum_b X[row][b] (+ Xlo[row][b]).
+__global__ __launch_bounds__(256) void rowsum_kernel(const __bf16* X, const __bf16* Xlo, int rows, int cols, int ld,
+                                                     float* out) {
     // One workgroup per row; 16-byte loads of 8 values when the row layout allows; fixed
     // summation order (per thread, then the wave butterfly, then the 4 waves in order).
     const int row = blockIdx.x;
     if (row >= rows) return;
-    const __bf16* xr = X + (size_t)row * ld;
+    const size_t roff = (size_t)row * ld;
     float s = 0.0f;
-    const bool vec = (cols % 8 == 0) && (ld % 8 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+    const bool vec = (cols % 8 == 0) && (ld % 8 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(Xlo) & 15) == 0);
     if (vec) {
         for (int c = threadIdx.x * 8; c < cols; c += blockDim.x * 8) {
-            const bf16x8 v = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(xr + c));
+            const bf16x8 v = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(X + roff + c));
+            if (Xlo) {
+                const bf16x8 l = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(Xlo + roff + c));
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s += (float)v[q];
+                for (int q = 0; q < 8; ++q) s += (float)v[q] + (float)l[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s += (float)v[q];
+            }
         }
     } else {
-        for (int c = threadIdx.x; c < cols; c += blockDim.x) s += (float)xr[c];
+        for (int c = threadIdx.x; c < cols; c += blockDim.x) s += (float)X[roff + c] + (Xlo ? (float)Xlo[roff + c] : 0.0f);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -215,12 +247,16 @@ hipError_t launch_gemm_nt(const GemmArgs& g, hipStream_t st) {
     if (g.M % 32 || g.N % 32 || g.K % 16 || g.splits < 1 || (g.K / g.splits) % 16 || g.K % g.splits)
         return hipErrorInvalidValue;
     const int waves = (g.M / 32) * (g.N / 32) * g.splits;
-    hipLaunchKernelGGL(gemm_nt_kernel, dim3((waves + 3) / 4), dim3(256), 0, st, g);
+    const dim3 grid((waves + 3) / 4), block(256);
+    if (g.A_lo && g.Bt_lo) hipLaunchKernelGGL((gemm_nt_kernel<true, true>), grid, block, 0, st, g);
+    else if (g.A_lo) hipLaunchKernelGGL((gemm_nt_kernel<true, false>), grid, block, 0, st, g);
+    else if (g.Bt_lo) hipLaunchKernelGGL((gemm_nt_kernel<false, true>), grid, block, 0, st, g);
+    else hipLaunchKernelGGL((gemm_nt_kernel<false, false>), grid, block, 0, st, g);
     return hipGetLastError();
 }
 
-hipError_t launch_rowsum(const __bf16* X, int rows, int cols, int ld, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(rowsum_kernel, dim3(rows), dim3(256), 0, st, X, rows, cols, ld, out);
+hipError_t launch_rowsum(const __bf16* X, const __bf16* Xlo, int rows, int cols, int ld, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(rowsum_kernel, dim3(rows), dim3(256), 0, st, X, Xlo, rows, cols, ld, out);
     return hipGetLastError();
 }
 

@@ -10,6 +10,11 @@ enum : int { kEpiPartial = 0, kEpiFwdHidden = 1, kEpiFwdOut = 2, kEpiBwdHidden =
 struct GemmArgs {
     const __bf16* A;    // M x K, row stride lda (elements)
     const __bf16* Bt;   // N x K, row stride ldb
+    // Optional low words of A and Bt (same layouts): an operand carried as a BF16 pair
+    // hi + lo (about 16 significant bits) contributes hi.b + lo.b (+ a.lo for the other side);
+    // the lo.lo product is dropped (relative size 2^-16 of each product).
+    const __bf16* A_lo;
+    const __bf16* Bt_lo;
     int M, N, K, lda, ldb, splits, epi;
     float* part;        // PARTIAL: [splits][M][N]
     const float* bias;  // FWD_*: N
@@ -18,6 +23,8 @@ struct GemmArgs {
     int ldh;
     __bf16* Aout;       // row-major output (ldo), may be null for BWD_HIDDEN
     __bf16* AoutT;      // transposed output (ldt)
+    __bf16* Aout_lo;    // low words of the stored outputs, v - hi rounded to BF16 (may be null)
+    __bf16* AoutT_lo;
     int ldo, ldt;
     const float* target;  // FWD_OUT: M x ld_target exact LLRs (nats)
     int ld_target, mout;
@@ -52,7 +59,8 @@ struct MlpInferArgs {
 };
 
 hipError_t launch_gemm_nt(const GemmArgs& g, hipStream_t st);
-hipError_t launch_rowsum(const __bf16* X, int rows, int cols, int ld, float* out, hipStream_t st);
+// Row sums of a BF16 matrix, with its low words Xlo (same layout) added when not null.
+hipError_t launch_rowsum(const __bf16* X, const __bf16* Xlo, int rows, int cols, int ld, float* out, hipStream_t st);
 hipError_t launch_reduce_splits(const float* part, int splits, size_t n, float* grad, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t st);
 // Several parameter tensors in one launch: tensor k owns the flat elements [start[k], start[k+1]).

@@ -1,13 +1,16 @@
 """Learned demapper on the GPU: gradients, Adam, inference, audit / fallback, training, checkpoints.
 
 * Per-symbol-variance exact LLRs (the training targets) against the FP64 oracle.
-* Gradients of one batch against the FP64 oracle network with the kernels' BF16 storage points
-  emulated (cosine >= 0.99999, max error <= 2e-3 RMS per tensor) and against the FP64 network on
-  the same BF16-rounded weights and inputs but unrounded activations and deltas (cosine >= 0.999,
-  max error <= 5e-2 RMS: BF16 storage of activations and deltas moves single entries by a few
-  per cent of the RMS, measured 3.6e-2 on W2).
+* Gradients of one batch against the FP64 oracle network on the same BF16-rounded weights and
+  inputs, activations and deltas unrounded: cosine >= 0.999 and max error <= 2e-2 RMS per
+  tensor.  As a secondary diagnostic, against the oracle network with the kernels' storage
+  points emulated (activations and deltas as BF16 hi + lo pairs): cosine >= 0.99999, max
+  error <= 2e-3 RMS.
 * Adam's first step against its closed form -lr g / (|g| + eps), g the GPU gradient.
-* Fused inference (LLRs and GMI) against the oracle network's forward pass.
+* Fused inference (LLRs and GMI) against the oracle network with BF16-rounded weights and
+  inputs only, element by element within a first-order bound derived from the kernel's operand
+  precision (BF16 activations, the layer-1 bias as a BF16 pair, FP32 accumulation); and, as a
+  diagnostic, against the oracle with the kernel's storage points emulated.
 * Every fallback reason, and that fallback results are the exact path's.
 * Training a 2D 16-point constellation brings the learned GMI close to the exact GMI, training an
   8D M = 2048 Gray product constellation passes the 0.01-bit audit at every SNR, and two
@@ -96,23 +99,24 @@ def test_gradients_match_oracle():
     const = dm.Constellation(c.points, c.labels)
     net = dm.MLP(const, w)
     grads, loss = net.gradients(_dev(y), _dev(s2), _dev(T))
-    # the oracle network with the kernels' BF16 storage points
-    out, cache = mlp.forward_stored(_w64(w), X)
-    ref = mlp.backward_stored(_w64(w), cache, out, T.astype(np.float64))
-    ref_loss = mlp.loss(out, T.astype(np.float64))
-    assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (loss, ref_loss)
-    # BF16-rounded weights and inputs, FP64 activations and deltas (no storage rounding inside)
+    T64 = T.astype(np.float64)
+    # the FP64 network on BF16-rounded weights and inputs; activations and deltas unrounded
     out_w, cache_w = mlp.forward_stored(_w64(w), X, rnd_act=mlp.identity)
-    ref_w = mlp.backward_stored(_w64(w), cache_w, out_w, T.astype(np.float64), rnd_act=mlp.identity)
+    ref_w = mlp.backward_stored(_w64(w), cache_w, out_w, T64, rnd_act=mlp.identity)
+    ref_loss = mlp.loss(out_w, T64)
+    assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (loss, ref_loss)
+    # diagnostic: the kernels' storage points (activations and deltas as BF16 hi + lo pairs)
+    out_p, cache_p = mlp.forward_stored(_w64(w), X, rnd_act=mlp.bf16x2_round)
+    ref_p = mlp.backward_stored(_w64(w), cache_p, out_p, T64, rnd_act=mlp.bf16x2_round)
     report, bad = {}, []
-    for k in ref:
+    for k in ref_w:
         gk = grads[k].astype(np.float64).ravel()
-        for name, r, cos_min, max_rel in (("stored", ref[k], 0.99999, 2e-3), ("bf16-weights", ref_w[k], 0.999, 5e-2)):
+        for name, r, cos_min, max_rel in (("bf16-weights", ref_w[k], 0.999, 2e-2), ("stored-pairs", ref_p[k], 0.99999, 2e-3)):
             r = r.ravel()
             rms = float(np.sqrt(np.mean(r * r)))
             cos = float(gk @ r / (np.linalg.norm(gk) * np.linalg.norm(r)))
             mx = float(np.max(np.abs(gk - r))) / rms
-            report[(k, name)] = (round(cos, 7), round(mx, 5))
+            report[(k, name)] = (round(cos, 7), round(mx, 6))
             if not (cos >= cos_min and mx <= max_rel):
                 bad.append((k, name, cos, mx))
     print("gradient agreement (cosine, max err / RMS):", report)
@@ -140,13 +144,44 @@ def test_adam_first_step_closed_form():
 
 def _infer_ref(w, y, sigma2):
     """Oracle forward with the inference kernel's storage: BF16 weights, inputs and activations,
-    the first-layer bias as a BF16 hi + lo pair."""
+    the first-layer bias as a BF16 hi + lo pair (diagnostic)."""
     b1 = np.asarray(w["b1"], dtype=np.float32)
     hi = mlp.bf16_round(b1)
     lo = mlp.bf16_round((b1 - hi.astype(np.float32)).astype(np.float32))
     X = mlp.features(y, _snr_of(sigma2))
     out, _ = mlp.forward_stored(_w64(w), X, b1=hi + lo)
     return out
+
+
+U_BF16 = 2.0 ** -8      # unit roundoff of BF16 (8 significant bits)
+U_PAIR = 2.0 ** -16     # a value carried as a BF16 hi + lo pair
+U_FP32 = 2.0 ** -24
+GELU_LIP = 1.13         # max |GELU'| of the tanh form (1.1289 near x = 1.5)
+U_GELU = 2.0 ** -20     # relative error of the kernel's GELU evaluation (exp2, reciprocal: ~1 ulp each)
+
+
+def _infer_bound(w, y, sigma2):
+    """The network with BF16-rounded weights and inputs only (activations unrounded) and a
+    first-order bound on how far the inference kernel may be from it per output:
+      layer 1:  dh1 <= 2^-16 |b1| + g_9 |X| |W1|            (bias as a BF16 pair, FP32 sums)
+      GELU:     da  <= L dh + (u + 2^-20) |a|                (L = max |GELU'|; a stored as BF16)
+      layer k:  dh  <= |W|^T da + g_256 |W|^T |a|            (FP32 accumulation, g_n = n u32)
+    Returns (out, bound)."""
+    wr = {k: (mlp.bf16_round(v) if k.startswith("W") else np.asarray(v, np.float64)) for k, v in w.items()}
+    X = mlp.bf16_round(mlp.features(y, _snr_of(sigma2)))
+    h1 = X @ wr["W1"] + wr["b1"]
+    a1 = mlp.gelu(h1)
+    h2 = a1 @ wr["W2"] + wr["b2"]
+    a2 = mlp.gelu(h2)
+    out = a2 @ wr["W3"] + wr["b3"]
+    aW1, aW2, aW3 = (np.abs(wr[k]) for k in ("W1", "W2", "W3"))
+    g = lambda n: n * U_FP32 / (1.0 - n * U_FP32)  # noqa: E731
+    dh1 = U_PAIR * np.abs(wr["b1"]) + g(X.shape[1] + 2) * (np.abs(X) @ aW1 + np.abs(wr["b1"]))
+    da1 = GELU_LIP * dh1 + (U_BF16 + U_GELU) * np.abs(a1)
+    dh2 = da1 @ aW2 + g(257) * (np.abs(a1) @ aW2 + np.abs(wr["b2"]))
+    da2 = GELU_LIP * dh2 + (U_BF16 + U_GELU) * np.abs(a2)
+    dout = da2 @ aW3 + g(257) * (np.abs(a2) @ aW3 + np.abs(wr["b3"]))
+    return out, dout
 
 
 def test_inference_matches_oracle_forward():
@@ -167,14 +202,22 @@ def test_inference_matches_oracle_forward():
     assert np.all(fb == 0) and np.all(np.isnan(loss))
     lab = c.labels[tx]
     for i, v in enumerate(s2):
-        ref = _infer_ref(w, ys[i], v)
         got = llrs[i].cpu().numpy().astype(np.float64)
-        rms = float(np.sqrt(np.mean(ref * ref)))
-        mx = float(np.max(np.abs(got - ref))) / rms
-        print(f"inference snr={snr[i]}: max err / RMS = {mx:.2e}")
-        assert mx <= 5e-3, (snr[i], mx)
+        ref, bound = _infer_bound(w, ys[i], v)
+        err = np.abs(got - ref)
+        print(f"inference snr={snr[i]}: max err {err.max():.2e}, max err / bound {np.max(err / bound):.3f}, "
+              f"mean bound {bound.mean():.2e}")
+        assert np.all(err <= bound), (snr[i], float(np.max(err / bound)))
+        # |d/dl log2(1 + e^{+-l})| <= 1/ln 2 per bit
         g_ref = oracle.gmi_from_llr(11, ref, lab)
-        assert abs(gmi[i] - g_ref) <= 1e-3, (snr[i], gmi[i], g_ref)
+        g_bound = float(np.mean(np.sum(bound, axis=1))) / np.log(2.0)
+        assert abs(gmi[i] - g_ref) <= g_bound + 1e-6, (snr[i], gmi[i], g_ref, g_bound)
+        # diagnostic: the kernel's storage points emulated
+        ref_s = _infer_ref(w, ys[i], v)
+        rms = float(np.sqrt(np.mean(ref_s * ref_s)))
+        mx = float(np.max(np.abs(got - ref_s))) / rms
+        print(f"inference snr={snr[i]}: vs emulated storage max err / RMS = {mx:.2e}")
+        assert mx <= 5e-3, (snr[i], mx)
 
 
 def test_inference_without_tx_and_empty_block():
