@@ -103,6 +103,28 @@ int dm_gmi_estimate(const dm_constellation* c, int n_snr, const double* sigma2,
                     double* gmi, double* mi, int prec, void* stream);
 
 /*
+ * dm_gmi_estimate without any device allocation, for callers that cannot allocate: code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (LLRs bit-identical, GMI / MI from the same fixed-point
+ * sums); the launch's scratch (GMI / MI slots, fix-up counts, a fix-up queue of 2^20
+ * symbols, about 16 MiB in all) is one static device array that each GPU the library runs on
+ * holds until the process ends.  No hipMalloc, hipFree or allocating library call is made:
+ * the constellation's MFMA operand tables are built by dm_constellation_create.
+ *   Limits: n_snr <= 32 (DM_EINVAL beyond: the array holds 32 noise levels); any N < 2^31
+ *   (a fix-up queue that fills up is recomputed in place by the demapping kernel).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's contents; each
+ * call clears what must start at zero with a fill kernel.  Calls on one GPU are serialised
+ * by a host lock held until the call has synchronised `stream`; launches that overlap the
+ * array from elsewhere (another process's library copy has its own array) would race.
+ * dm_last_fixup_count reports no counts after this call (it returns DM_EINVAL).
+ * Errors: as dm_gmi_estimate; DM_EUNSUPPORTED also when an operand table is missing (after
+ * the points were replaced in place).
+ */
+int dm_gmi_estimate_noalloc(const dm_constellation* c, int n_snr, const double* sigma2,
+                            const float* const* y, const uint16_t* tx, int64_t N,
+                            float* const* llr, double* gmi, double* mi, int prec, void* stream);
+
+/*
  * Batched demapping of many instances (constellation, noise level, block) of uneven M, D and
  * N in one persistent launch (the GMI of many candidate constellations, as the paper's
  * shaping search evaluates, Sec. 5).  All instances share one operand precision `prec`;

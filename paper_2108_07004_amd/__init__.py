@@ -54,6 +54,8 @@ def load_library():
     lib.dm_demap_llr.restype = I
     lib.dm_gmi_estimate.argtypes = [P, I, P, P, P, I64, P, P, P, I, P]
     lib.dm_gmi_estimate.restype = I
+    lib.dm_gmi_estimate_noalloc.argtypes = [P, I, P, P, P, I64, P, P, P, I, P]
+    lib.dm_gmi_estimate_noalloc.restype = I
     lib.dm_last_fixup_count.argtypes = [P, I]
     lib.dm_last_fixup_count.restype = I64
     lib.dm_probe_valu_rates.argtypes = [P, P]
@@ -198,7 +200,7 @@ def demap_llr(const: Constellation, sigma2: float, y, llr=None, prec: str = "fp3
 
 
 def gmi_estimate(const: Constellation, sigma2: Sequence[float], ys, tx, llrs=None, prec: str = "fp32",
-                 stream=None, want_mi: bool = True):
+                 stream=None, want_mi: bool = True, _entry: str = "dm_gmi_estimate"):
     """Monte-Carlo GMI (and MI) in bits/symbol at each noise variance.
 
     ys: list of n_snr tensors (N x D FP32) or one (n_snr, N, D) tensor.
@@ -220,11 +222,18 @@ def gmi_estimate(const: Constellation, sigma2: Sequence[float], ys, tx, llrs=Non
         lptr = (ctypes.c_void_p * ns)(*[_dev_tensor(t, ("float32",), (N, const.m), "llr[s]").value for t in llist])
     gmi = np.empty(ns, dtype=np.float64)
     mi = np.empty(ns, dtype=np.float64) if want_mi else None
-    _check(load_library().dm_gmi_estimate(
+    _check(getattr(load_library(), _entry)(
         const.handle, ns, s2.ctypes.data_as(ctypes.c_void_p), ctypes.cast(yptr, ctypes.c_void_p), txp, N,
         None if lptr is None else ctypes.cast(lptr, ctypes.c_void_p), gmi.ctypes.data_as(ctypes.c_void_p),
         None if mi is None else mi.ctypes.data_as(ctypes.c_void_p), PREC[prec], _stream_handle(stream)))
     return gmi, mi
+
+
+def gmi_estimate_noalloc(const: Constellation, sigma2: Sequence[float], ys, tx, llrs=None, prec: str = "fp32",
+                         stream=None, want_mi: bool = True):
+    """gmi_estimate through dm_gmi_estimate_noalloc: no device allocation (static scratch),
+    at most 32 noise levels per call."""
+    return gmi_estimate(const, sigma2, ys, tx, llrs, prec, stream, want_mi, _entry="dm_gmi_estimate_noalloc")
 
 
 def last_fixup_count(n_snr: int):

@@ -41,6 +41,8 @@ void clear_error();
 int hip_fail(hipError_t e, const char* what);
 
 int check_device_ptr(const void* p, const char* name, int device);
+// Drop the per-point fix-up counts of the last GMI call (dm_last_fixup_count then fails).
+void forget_fix_counts();
 int check_current_device(const dm_constellation* c);
 int validate_sigma2(double s2);
 float exponent_scale(double sigma2);
@@ -49,6 +51,21 @@ float exponent_scale(double sigma2);
 int ensure_frag(dm_constellation* c, int prec, bool pad8);
 int ensure_table8(dm_constellation* c);
 
+// Device scratch of one exact-path launch: fixed-point GMI / MI slots [kMaxSnrPerLaunch][kAccSlots][2],
+// fix-up pair counts [kMaxSnrPerLaunch] + bad-tx flag, fix-up queue and its counter.
+struct ChunkScratch {
+    unsigned long long* acc;
+    uint32_t* fix_pairs;
+    uint32_t* queue_count;
+    dm::FixEntry* queue;
+    uint32_t queue_cap;
+};
+// Exact path over up to 32 SNR points of one block on the given scratch, which the caller has
+// cleared (acc and fix_pairs when want_acc, queue_count always); allocates nothing (an MFMA
+// precision needs its operand table built).  Caller holds c->mu.
+int run_chunk_on(dm_constellation* c, const ChunkScratch& scr, int n_snr, const double* sigma2,
+                 const float* const* y, const uint16_t* tx, int64_t N, float* const* llr, bool want_acc, int prec,
+                 hipStream_t st, const float* sigma2_sym, bool allow_prof);
 // Exact path over up to 32 SNR points of one block (scratch of c; caller holds c->mu).
 // sigma2_sym, when not null, gives each symbol its own noise variance (sigma2 is then unused).
 int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,

@@ -47,6 +47,11 @@ hipEvent_t prof_event() {
 
 void clear_error() { g_err.clear(); }
 
+void forget_fix_counts() {
+    g_fix_counts.clear();  // keeps its capacity: no deallocation
+    g_have_fix = false;
+}
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -125,9 +130,6 @@ LaunchArgs base_args(const dm_constellation* c, int64_t N) {
     a.K = (float)(123 - c->m);
     a.flag_thresh = std::ldexp(1.0f, c->m - 102);
     a.near_thresh = std::ldexp(1.0f, c->m - 42);
-    a.sinks.queue = c->d_queue;
-    a.sinks.queue_count = c->d_queue_count;
-    a.sinks.queue_cap = c->queue_cap;
     return a;
 }
 
@@ -239,9 +241,12 @@ int validate_sigma2(double s2) {
     return DM_OK;
 }
 
-// Run the demapper over up to kMaxSnrPerLaunch SNR points of one block.
-int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
-              int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st, const float* sigma2_sym) {
+// Run the demapper over up to kMaxSnrPerLaunch SNR points of one block, with the accumulators,
+// flags and fix-up queue of `scr` (cleared by the caller).  Allocates nothing: an MFMA
+// precision needs its operand table already built.
+int run_chunk_on(dm_constellation* c, const ChunkScratch& scr, int n_snr, const double* sigma2,
+                 const float* const* y, const uint16_t* tx, int64_t N, float* const* llr, bool want_acc, int prec,
+                 hipStream_t st, const float* sigma2_sym, bool allow_prof) {
     if (prec != DM_PREC_FP32) {
         if (c->D > 8) return fail(DM_EUNSUPPORTED, "MFMA precisions support D <= 8 (D=%d)", c->D);
         if (c->M < 32) return fail(DM_EUNSUPPORTED, "MFMA precisions need M >= 32 (M=%d)", c->M);
@@ -251,36 +256,32 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
                 if (exponent_scale(sigma2[s]) >= 30000.0f)
                     return fail(DM_EUNSUPPORTED, "sigma2 %g is too small for FP16 operands", sigma2[s]);
         }
-        int rr = ensure_frag(c, prec, false);
-        if (rr) return rr;
+        if (!c->d_frag[prec] || !c->d_pv[prec])
+            return fail(DM_EUNSUPPORTED, "the operand table of precision %d is not built for this constellation", prec);
     }
     const int tile = prec == DM_PREC_FP32 ? dm::valu_tile_symbols() : dm::mfma_block_symbols();
     const int64_t tiles_per_snr = (N + tile - 1) / tile;
-    int r = ensure_scratch(c, (uint64_t)N * n_snr);
-    if (r) return r;
     LaunchArgs a = base_args(c, N);
     a.tx = tx;
     a.tiles_per_snr = tiles_per_snr;
     a.n_snr = n_snr;
     a.want_llr = llr ? 1 : 0;
     a.sigma2_sym = sigma2_sym;
-    a.sinks.acc = want_acc ? c->d_acc : nullptr;
-    a.sinks.fix_pairs = want_acc ? c->d_fix_pairs : nullptr;
-    a.sinks.bad_tx = want_acc ? c->d_fix_pairs + dm::kMaxSnrPerLaunch : nullptr;
+    a.sinks.acc = want_acc ? scr.acc : nullptr;
+    a.sinks.fix_pairs = want_acc ? scr.fix_pairs : nullptr;
+    a.sinks.bad_tx = want_acc ? scr.fix_pairs + dm::kMaxSnrPerLaunch : nullptr;
+    a.sinks.queue = scr.queue;
+    a.sinks.queue_count = scr.queue_count;
+    a.sinks.queue_cap = scr.queue_cap;
     for (int s = 0; s < n_snr; ++s) {
         a.snr[s].y = y[s];
         a.snr[s].llr = llr ? llr[s] : nullptr;
         a.snr[s].c = exponent_scale(sigma2[s]);
     }
-    if (want_acc) {
-        DM_HIP_TRY(hipMemsetAsync(c->d_acc, 0, sizeof(unsigned long long) * n_snr * dm::kAccSlots * 2, st));
-        DM_HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
-    }
-    DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
     const int grid = persistent_grid(c, tiles_per_snr * n_snr, prec == DM_PREC_FP32 ? 2 : 1);
     const int fix_grid = c->cus * dm::fixup_blocks_per_cu(c->M);
     ProfRec pr{nullptr, nullptr, nullptr};
-    if (g_prof_on) {
+    if (g_prof_on && allow_prof) {
         pr = ProfRec{prof_event(), prof_event(), prof_event()};
         if (pr.e0) DM_HIP_TRY(hipEventRecord(pr.e0, st));
     }
@@ -293,6 +294,21 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
         g_prof.push_back(pr);
     }
     return DM_OK;
+}
+
+// The same with the constellation's own scratch, grown (and the operand table built) as needed.
+int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float* const* y, const uint16_t* tx,
+              int64_t N, float* const* llr, bool want_acc, int prec, hipStream_t st, const float* sigma2_sym) {
+    int r;
+    if (prec != DM_PREC_FP32 && c->D <= 8 && c->M >= 32 && (r = ensure_frag(c, prec, false))) return r;
+    if ((r = ensure_scratch(c, (uint64_t)N * n_snr))) return r;
+    if (want_acc) {
+        DM_HIP_TRY(hipMemsetAsync(c->d_acc, 0, sizeof(unsigned long long) * n_snr * dm::kAccSlots * 2, st));
+        DM_HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
+    }
+    DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
+    const ChunkScratch scr{c->d_acc, c->d_fix_pairs, c->d_queue_count, c->d_queue, c->queue_cap};
+    return run_chunk_on(c, scr, n_snr, sigma2, y, tx, N, llr, want_acc, prec, st, sigma2_sym, true);
 }
 
 int llr_var_run(dm_constellation* c, const float* sigma2_sym, const float* y, int64_t N, float* llr, int prec,
@@ -424,6 +440,16 @@ int dm_constellation_create(const float* points, const uint16_t* labels, int32_t
         dm_constellation_destroy(c);
         return hip_fail(e, "constellation upload");
     }
+    // MFMA operand tables of every precision are built here, once, so that later calls (the
+    // allocation-free GMI entry point among them) find them ready.
+    if (M >= 32 && D <= 8)
+        for (int prec = DM_PREC_BF16; prec <= DM_PREC_FP16X3; ++prec) {
+            const int r = ensure_frag(c, prec, false);
+            if (r) {
+                dm_constellation_destroy(c);
+                return r;
+            }
+        }
     *out = c;
     return DM_OK;
 }
