@@ -144,6 +144,7 @@ int mfma_slots(int D, bool split) {
 int mfma_block_symbols() { return (kMfmaThreads / 64) * 32; }
 
 hipError_t launch_demap_mfma(const LaunchArgs& a, int prec, const void* frag, const void* pv, int grid, hipStream_t st) {
+    if (mfma_small_supported(a.M, a.D)) return launch_demap_mfma_small(a, prec, frag, pv, grid, st);
     switch (prec) {
         case 1: return launch_d<__bf16, false>(a, frag, pv, grid, st);
         case 2: return launch_d<_Float16, false>(a, frag, pv, grid, st);

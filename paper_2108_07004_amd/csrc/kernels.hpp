@@ -40,6 +40,12 @@ int mfma_slots(int D, bool split);
 // Symbols per block iteration of the MFMA kernel.
 int mfma_block_symbols();
 
+// MFMA demapper specialised for M = 32..256 points and D in {2, 4, 8} (tile count and label
+// bits known at compile time); hipErrorNotSupported for other shapes.
+bool mfma_small_supported(int M, int D);
+hipError_t launch_demap_mfma_small(const LaunchArgs& a, int prec, const void* frag, const void* pv, int grid,
+                                   hipStream_t st);
+
 // MFMA demapper: prec 1 = BF16, 2 = FP16, 3 = BF16 split, 4 = FP16 split.  `frag` is the
 // point-side operand table in fragment order ([tile][mfma][lane] x 16 bytes); `pv` the same
 // operands per label ([label][K slots], 16-bit), read for the transmitted points.

@@ -258,33 +258,21 @@ __device__ __forceinline__ void mfma_tiles(const uint4* lds_frag, int lane, int 
     }
 }
 
-// Combine the two lanes of each symbol, write LLRs, flag and queue underflowed bits and form
-// the per-symbol GMI (both halves) and MI (half 0) terms.  txl is the symbol's transmitted label
-// (0 without tx), loaded by the caller before the tile loop so that its latency is hidden.
-template <typename T, int D, bool SPLIT>
-__device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k, const uint16_t* pv,
-                                              const Frags<T, Slots<D, SPLIT>::S>& bfr, const MfmaAcc& A,
-                                              int64_t n, bool active, bool bad, int txl, int lane, float& g,
-                                              float& mi) {
-    using V = typename Mma<T>::V;
-    constexpr int S = Slots<D, SPLIT>::S;
-    const int h = lane >> 5;
-    const int m = b.m;
+// Per-half subset sums of every label bit from the tile-loop accumulators: S0[p] / S1[p] sum
+// this lane half's points whose label bit p is 0 / 1, tot all of them.  Bits 0-3 index the
+// 16 registers: their marginals share one pairwise tree (P: pairs over bit 0, Q: pairs of P
+// over bit 1); bit 4 is the lane half; bits 5-6 and 7-8 index accB and accC; higher bits were
+// summed per 512-label block.
+__device__ __forceinline__ void mfma_subset_sums(const MfmaAcc& A, int h, float (&S0)[16], float (&S1)[16],
+                                                 float& tot) {
     const float (&accA)[16] = A.accA;
     const float (&accB)[4] = A.accB;
     const float (&accC)[4] = A.accC;
-    const float (&hi0)[7] = A.hi0;
-    const float (&hi1)[7] = A.hi1;
-    // Per-half subset sums of every label bit, then combine the two lanes (l, l^32) of each
-    // symbol.  Bits 0-3 index the 16 registers: their marginals share one pairwise tree
-    // (P: pairs over bit 0, Q: pairs of P over bit 1); bit 4 is the lane half; bits 5-6 and
-    // 7-8 index accB and accC; higher bits were summed per 512-label block.
     float P[8], Q[4];
 #pragma unroll
     for (int q = 0; q < 8; ++q) P[q] = accA[2 * q] + accA[2 * q + 1];
 #pragma unroll
     for (int u = 0; u < 4; ++u) Q[u] = P[2 * u] + P[2 * u + 1];
-    float S0[16], S1[16];
     S0[0] = ((accA[0] + accA[2]) + (accA[4] + accA[6])) + ((accA[8] + accA[10]) + (accA[12] + accA[14]));
     S1[0] = ((accA[1] + accA[3]) + (accA[5] + accA[7])) + ((accA[9] + accA[11]) + (accA[13] + accA[15]));
     S0[1] = (P[0] + P[2]) + (P[4] + P[6]);
@@ -293,7 +281,7 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     S1[2] = Q[1] + Q[3];
     S0[3] = Q[0] + Q[1];
     S1[3] = Q[2] + Q[3];
-    const float tot = S0[3] + S1[3];
+    tot = S0[3] + S1[3];
     S0[4] = h ? 0.0f : tot;
     S1[4] = h ? tot : 0.0f;
     S0[5] = accB[0] + accB[2];
@@ -306,17 +294,36 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     S1[8] = accC[2] + accC[3];
 #pragma unroll
     for (int p = 9; p < 16; ++p) {
-        S0[p] = hi0[p - 9];
-        S1[p] = hi1[p - 9];
+        S0[p] = A.hi0[p - 9];
+        S1[p] = A.hi1[p - 9];
     }
+}
+
+// Combine the two lanes of each symbol, write LLRs, flag and queue underflowed bits and form
+// the per-symbol GMI (both halves) and MI (half 0) terms, from this half's subset sums S0 / S1
+// and total tot.  MB < 16: the constellation has exactly MB label bits (known at compile
+// time); MB == 16: b.m bits.  txl is the symbol's transmitted label (0 without tx), loaded by
+// the caller before the tile loop so that its latency is hidden.
+template <typename T, int D, bool SPLIT, int MB>
+__device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, const uint16_t* pv,
+                                            const Frags<T, Slots<D, SPLIT>::S>& bfr, const float (&S0)[MB],
+                                            const float (&S1)[MB], float tot, int64_t n, bool active, bool bad,
+                                            int txl, int lane, float& g, float& mi) {
+    using V = typename Mma<T>::V;
+    constexpr int S = Slots<D, SPLIT>::S;
+    constexpr int NJ = (MB + 1) / 2;
+    const int h = lane >> 5;
+    const int m = MB < 16 ? MB : b.m;
     // Combine with the partner lane: half h finishes bit 2j + h of every pair (2j, 2j+1) as
     // its own partial sum plus the partner's.
-    float c0[8], c1[8];
+    float c0[NJ], c1[NJ];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (2 * j < m) {
-            c0[j] = half_pair_sum(S0[2 * j], S0[2 * j + 1]);
-            c1[j] = half_pair_sum(S1[2 * j], S1[2 * j + 1]);
+            const float a0 = S0[2 * j], a1 = S1[2 * j];
+            const float b0 = 2 * j + 1 < MB ? S0[2 * j + 1] : 0.0f, b1 = 2 * j + 1 < MB ? S1[2 * j + 1] : 0.0f;
+            c0[j] = half_pair_sum(a0, b0);
+            c1[j] = half_pair_sum(a1, b1);
         }
     }
     const bool bad_sym = half_or((uint32_t)bad) != 0;
@@ -336,9 +343,9 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     int hv = h;
     asm volatile("" : "+v"(hv));
     uint32_t flagged = 0;
-    float Lv[8];
+    float Lv[NJ];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (2 * j < m) {
             const int p = 2 * j + hv;
             const bool valid = p < m;  // false only in half 1 for the top bit of an odd m
@@ -356,12 +363,12 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
     if (b.llr && active) {
         float* col = b.llr + (size_t)n * m + (m - 1 - hv);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
+        for (int j = 0; j < NJ; ++j)
             if (2 * j < m && 2 * j + hv < m) col[-2 * j] = Lv[j];
     }
     if (flagged) {  // rare: the GMI-only shortcut, else the exact fix-up
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             if (2 * j < m) {
                 const int p = 2 * j + h;
                 const float s0 = c0[j], s1 = c1[j];
@@ -415,6 +422,18 @@ __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k
         g += (float)gc;
         mi += (float)mc;
     }
+}
+
+
+// The generic epilogue: subset sums from the accumulators, then mfma_finish over b.m bits.
+template <typename T, int D, bool SPLIT>
+__device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k, const uint16_t* pv,
+                                              const Frags<T, Slots<D, SPLIT>::S>& bfr, const MfmaAcc& A,
+                                              int64_t n, bool active, bool bad, int txl, int lane, float& g,
+                                              float& mi) {
+    float S0[16], S1[16], tot;
+    mfma_subset_sums(A, lane >> 5, S0, S1, tot);
+    mfma_finish<T, D, SPLIT, 16>(b, k, pv, bfr, S0, S1, tot, n, active, bad, txl, lane, g, mi);
 }
 
 }  // namespace dm

@@ -82,7 +82,7 @@ def test_mfma_precision_parity(prec, name, N):
             json.dump(_TABLE, f, indent=1)
 
 
-@pytest.mark.parametrize("M,D", [(32, 1), (64, 3), (128, 8), (512, 5), (4096, 2), (8192, 4)])
+@pytest.mark.parametrize("M,D", [(32, 1), (64, 3), (128, 8), (512, 5), (4096, 2), (8192, 4), (32, 4), (64, 8), (256, 2)])
 def test_mfma_shapes(M, D):
     g = W.rng(51, "misc", M, D)
     pts = g.standard_normal((M, D))
