@@ -97,28 +97,41 @@ def bench_batched(prec, steps, warmup):
         y_t = W.awgn_torch(inst.const.points, tx_t, torch.from_numpy(z).to(dev), inst.sigma2)
         llr = torch.empty((inst.N, inst.const.m), dtype=torch.float32, device=dev)
         items.append((consts[key], inst.sigma2, y_t, tx_t, llr))
+    def time_plan(plan):
+        for _ in range(warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # the fixed-shape plan (MFMA body where it applies, one tile per work item, claims of 4)
+    fixed = dm.Plan(items, prec=prec, autotune=False)
+    ms_fixed = time_plan(fixed)
+    fixed.close()
     t0 = time.perf_counter()
     plan = dm.Plan(items, prec=prec, autotune=True)
     t_plan = time.perf_counter() - t0
-    kinds, ns = plan.info()
-    for _ in range(warmup):
-        plan.launch()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        plan.launch()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    kinds, ns, sym = plan.info()
+    n_items, grab, grid = plan.stats()
+    ms = time_plan(plan)
     gmi, mi, fx = plan.results()
     n_sym = sum(i.N for i in insts)
     pairs = float(sum(i.N * i.const.M for i in insts))
     peak = FULL_RATE / EXP2_ISSUE_CYCLES
+    shapes = {}
+    for inst, k, sy in zip(insts, kinds, sym):
+        shapes[f"M{inst.const.M}/D{inst.const.D}"] = f"{'mfma' if k == 1 else 'fp32'} x {int(sy)} symbols"
     return {"workload": "64 instances: M in {16,64,256,1024,2048}, D in {2,4,8}, N log-uniform 2^14..2^22, "
                         "SNR U[0,20] dB, one hipGraph launch (zero-fill + persistent kernel + fix-up)",
             "symbols": n_sym, "exp2_per_launch": pairs, "ms_per_launch": ms, "symbols_per_s": n_sym / (ms * 1e-3),
             "exp2_frac_of_peak": pairs / (ms * 1e-3) / peak, "plan_create_s": t_plan,
+            "fixed_shape_ms_per_launch": ms_fixed, "autotune_speedup": ms_fixed / ms,
+            "shape": {"claim_items": grab, "work_items": n_items, "workgroups": grid, "per_class": shapes},
             "mfma_instances": int(np.sum(kinds == 1)), "fp32_instances": int(np.sum(kinds == 0)),
             "fixup_pairs": int(np.sum(fx)), "prec": prec}
 
@@ -178,6 +191,43 @@ def bench_learned(const, w, ys, tx_t, llrs, exact_gmi, exact_sym_per_s, exact_pr
                                       "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
                                       "frac": flops / dt_net / MFMA_BF16_PEAK, "traffic": None}},
     }
+
+
+def bench_learned_sweep(const, w, ys, tx_t, batch, n_eval=1 << 18,
+                        budgets=((1 << 26, 1), (1 << 26, 2), (1 << 26, 4), (1 << 27, 1), (1 << 28, 1))):
+    """GMI loss of the learned demapper on the 8D M = 2048 random constellation against its
+    training budget: for each (samples, epochs), a network trained from the same start, then
+    exact GMI - learned GMI at every SNR point on the first n_eval symbols of the headline block."""
+    import torch
+
+    import paper_2108_07004_amd as dm
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    ys_e = [y[:n_eval] for y in ys]
+    tx_e = tx_t[:n_eval]
+    g_ex, _ = dm.gmi_estimate(const, w.sigma2, ys_e, tx_e, prec="fp32")
+    rows = []
+    for n_train, epochs in budgets:
+        y_tr, s2_tr = W.mlp_samples_torch(w.const.points, n_train, 0.0, 15.0, dev)
+        net = dm.MLP(const, W.mlp_init_weights(w.const.D, 256, w.const.m))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = net.train(const, y_tr, s2_tr, batch=batch, epochs=epochs, lr=2e-3, lr_final=2e-5, target_prec="fp32",
+                         snr_range=(0.0, 15.0))
+        t_train = time.perf_counter() - t0
+        del y_tr, s2_tr
+        g_l, _, _ = dm.demap_learned(net, const, w.sigma2, ys_e, tx_e, None, max_gmi_loss=-1.0)
+        gl = [round(float(a - b), 4) for a, b in zip(g_ex, g_l)]
+        log(f"learned sweep: {n_train} samples x {epochs} epochs, {t_train:.1f} s, final loss {loss:.4g}, "
+            f"GMI loss {min(gl):.3f}..{max(gl):.3f} bit")
+        rows.append({"samples": n_train, "epochs": epochs, "train_s": round(t_train, 2),
+                     "final_loss": float(loss), "gmi_loss": gl})
+        del net
+        torch.cuda.empty_cache()
+    return {"workload": f"train U[0,15] dB, batch {batch}, Adam 2e-3 -> 2e-5 cosine, (D+1)-256-256-m; "
+                        f"evaluate on the first {n_eval} symbols of {w.name} at its {len(w.sigma2)} SNR points",
+            "exact_gmi": [round(float(v), 5) for v in g_ex], "runs": rows}
 
 
 def bench_learned_product(w, tx_t, llrs, exact_prec, n_train, batch, steps):
@@ -378,6 +428,8 @@ def main():
     ap.add_argument("--no-gs", action="store_true", help="skip the shaping-search measurement")
     ap.add_argument("--learned-train", type=int, default=1 << 26, help="training samples of the learned demapper")
     ap.add_argument("--learned-batch", type=int, default=4096)
+    ap.add_argument("--learned-sweep", action="store_true",
+                    help="also train the learned demapper at several sample / epoch budgets (GMI loss per budget)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -522,6 +574,9 @@ def main():
         log(f"learned: pam8d learned {lp['learned_symbols_per_s'] / 1e9:.3f} vs exact "
             f"{lp['exact_symbols_per_s'] / 1e9:.3f} Gsym/s ({lp['speedup_vs_exact']:.2f}x), max GMI loss "
             f"{lp['max_gmi_loss_vs_exact']:.4f} bit, fallback {set(lp['fallback'])}")
+    if args.learned_sweep and w.name == "gauss8d2048":
+        log("learned sweep: GMI loss against training budget")
+        out["learned_sweep"] = bench_learned_sweep(const, w, ys, tx_t, args.learned_batch)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w, tx, z, args.cpu_sample)

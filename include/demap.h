@@ -127,11 +127,16 @@ int dm_gmi_estimate_noalloc(const dm_constellation* c, int n_snr, const double* 
 /*
  * Batched demapping of many instances (constellation, noise level, block) of uneven M, D and
  * N in one persistent launch (the GMI of many candidate constellations, as the paper's
- * shaping search evaluates, Sec. 5).  All instances share one operand precision `prec`;
- * each instance runs the FP32 direct-difference body or the MFMA body, chosen per
- * (M, D, prec) by timing both when DM_PLAN_AUTOTUNE is set (results cached per GPU arch in
- * the file named by the environment variable DM_AUTOTUNE_CACHE, if set), by a fixed rule
- * otherwise, or forced with DM_PLAN_FORCE_VALU / DM_PLAN_FORCE_MFMA.
+ * shaping search evaluates, Sec. 5).  All instances share one operand precision `prec`.
+ * Launch shape: each (M, D, prec) class runs the FP32 direct-difference body or the MFMA body
+ * with work items of 1, 2 or 4 of that body's symbol tiles (1024 symbols for FP32, 512 for
+ * MFMA), and workgroups claim 1, 2, 4 or 8 work items at a time.  With DM_PLAN_AUTOTUNE the
+ * body and item size are chosen per class by timing every pair on a probe block that fills
+ * the GPU (results cached per GPU arch in the file named by the environment variable
+ * DM_AUTOTUNE_CACHE, if set) and the claim size by timing the whole plan at each; otherwise a
+ * fixed rule (MFMA where it applies, one tile per item, claims of 4).  DM_PLAN_FORCE_VALU /
+ * DM_PLAN_FORCE_MFMA force the body, DM_PLAN_ITEMS(k) items of 2^(k-1) tiles (k = 1..3),
+ * DM_PLAN_CLAIM(k) claims of 2^(k-1) items (k = 1..4); the autotuner then picks the rest.
  * Limits: D <= 8 and M <= 4096 per instance (M <= 2048 for split MFMA operands).
  */
 typedef struct dm_instance {
@@ -144,6 +149,8 @@ typedef struct dm_instance {
 } dm_instance;
 
 enum { DM_PLAN_AUTOTUNE = 1, DM_PLAN_FORCE_VALU = 2, DM_PLAN_FORCE_MFMA = 4 };
+#define DM_PLAN_ITEMS(k) ((int)(k) << 8)   /* force work items of 2^(k-1) symbol tiles, k = 1..3 */
+#define DM_PLAN_CLAIM(k) ((int)(k) << 12)  /* force claims of 2^(k-1) work items, k = 1..4 */
 
 typedef struct dm_plan dm_plan;
 
@@ -165,8 +172,9 @@ int dm_plan_launch(dm_plan* plan, void* stream);
  * instances without tx or with N == 0) and fix-up pair counts (HOST int64, or NULL). */
 int dm_plan_results(dm_plan* plan, double* gmi, double* mi, int64_t* fixup_pairs, void* stream);
 
-/* Per-instance kernel body chosen (0 = FP32, 1 = MFMA) and its cost in ns per (symbol, point). */
-int dm_plan_info(const dm_plan* plan, int* kinds, double* ns_per_pair);
+/* Per-instance launch shape (any output may be NULL): kernel body (0 = FP32, 1 = MFMA), its
+ * cost in ns per (symbol, point) and the symbols per work item. */
+int dm_plan_info(const dm_plan* plan, int* kinds, double* ns_per_pair, int32_t* item_symbols);
 
 /* Launch shape of a plan (any output may be NULL): work items in its list, items a workgroup
  * claims at a time, and workgroups of the persistent launch. */

@@ -70,7 +70,7 @@ def load_library():
     lib.dm_plan_launch.restype = I
     lib.dm_plan_results.argtypes = [P, P, P, P, P]
     lib.dm_plan_results.restype = I
-    lib.dm_plan_info.argtypes = [P, P, P]
+    lib.dm_plan_info.argtypes = [P, P, P, P]
     lib.dm_plan_info.restype = I
     lib.dm_plan_stats.argtypes = [P, P, P, P]
     lib.dm_plan_stats.restype = I
@@ -296,13 +296,21 @@ class Plan:
     The plan keeps references to every tensor it was built with (their memory must stay valid).
     """
 
-    def __init__(self, items, prec: str = "fp16x3", autotune: bool = True, force: str | None = None):
+    def __init__(self, items, prec: str = "fp16x3", autotune: bool = True, force: str | None = None,
+                 item_tiles: int | None = None, claim: int | None = None):
+        """force: None / "valu" / "mfma" (kernel body); item_tiles: None or 1, 2, 4 (symbol tiles
+        per work item); claim: None or 1, 2, 4, 8 (work items per claim).  With autotune the
+        unforced parts of the shape are timed, else a fixed rule fills them."""
         self._items = list(items)
         flags = PLAN_AUTOTUNE if autotune else 0
         if force == "valu":
-            flags = PLAN_FORCE_VALU
+            flags |= PLAN_FORCE_VALU
         elif force == "mfma":
-            flags = PLAN_FORCE_MFMA
+            flags |= PLAN_FORCE_MFMA
+        if item_tiles is not None:
+            flags |= {1: 1, 2: 2, 4: 3}[item_tiles] << 8
+        if claim is not None:
+            flags |= {1: 1, 2: 2, 4: 3, 8: 4}[claim] << 12
         self._arr = _instances(self._items)
         h = ctypes.c_void_p()
         _check(load_library().dm_plan_create(ctypes.cast(self._arr, ctypes.c_void_p), len(self._items), PREC[prec],
@@ -323,11 +331,13 @@ class Plan:
         return g, mi, fx
 
     def info(self):
+        """(kernel body per instance: 0 FP32 / 1 MFMA, ns per pair, symbols per work item)."""
         kinds = np.empty(self.n, dtype=np.int32)
         ns = np.empty(self.n, dtype=np.float64)
+        sym = np.empty(self.n, dtype=np.int32)
         _check(load_library().dm_plan_info(self._h, kinds.ctypes.data_as(ctypes.c_void_p),
-                                           ns.ctypes.data_as(ctypes.c_void_p)))
-        return kinds, ns
+                                           ns.ctypes.data_as(ctypes.c_void_p), sym.ctypes.data_as(ctypes.c_void_p)))
+        return kinds, ns, sym
 
     def stats(self):
         """(work items, items per claim, workgroups) of the plan's launch."""

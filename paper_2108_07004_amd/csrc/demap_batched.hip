@@ -1,19 +1,21 @@
 // Batched exact demapping: one persistent launch over many (constellation, noise level, block)
 // instances of uneven M, D and N (gfx950).
 //
-// Work items are (instance, symbol tile) pairs listed instance by instance, the most costly
-// instance first.  Workgroups claim fixed chunks of `grab` consecutive items from a counter
+// Work items are (instance, sub consecutive symbol tiles) pairs listed instance by instance,
+// the most costly instance first (sub per instance, from the plan's shape choice).  Workgroups claim fixed chunks of `grab` consecutive items from a counter
 // (dynamic balance: the cheap items at the end fill the tail) and restage their LDS table only
 // when the next item belongs to another instance.  GMI / MI partial sums are flushed per chunk
 // and instance, so every fixed-point contribution covers a fixed set of symbols whichever
 // workgroup runs it: the totals are bit-reproducible.  Each instance runs either
 // the FP32 direct-difference body (one lane per symbol, 1024-symbol tiles) or the MFMA body
-// (one wave per 32 symbols, 512-symbol tiles), as chosen per (M, D) by the autotuner.  Batched
+// (one wave per 32 symbols, 512-symbol tiles; 32..256-point constellations take the
+// compile-time tile loop of mfma_small.hpp), as chosen per (M, D) by the autotuner.  Batched
 // tables use a row stride of 8 (D <= 8 zero-padded): the padded coordinates contribute exact
 // zeros, and the MFMA operand vectors of every instance have the same K layout.
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "mfma_body.hpp"
+#include "mfma_small.hpp"
 #include "valu_body.hpp"
 
 namespace dm {
@@ -22,6 +24,18 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
+
+// One 32-symbol batch of an instance with 32 * NT points (D padded to 8): compile-time tile loop
+// and epilogue.
+template <typename T, bool SPLIT, int NT>
+__device__ __forceinline__ void small_item(const uint4* lds, const BlockView& b, const Sinks& k, const uint16_t* pv,
+                                           const Frags<T, Slots<8, SPLIT>::S>& bfr, int64_t n, bool active, bool bad,
+                                           int txl, int lane, float& g, float& mi) {
+    constexpr int MB = SmallBits<NT>::MB;
+    float S0[MB], S1[MB], tot;
+    mfma_small_sums<T, 8, SPLIT, NT>(lds, lane, bfr, S0, S1, tot);
+    mfma_finish<T, 8, SPLIT, MB>(b, k, pv, bfr, S0, S1, tot, n, active, bad, txl, lane, g, mi);
+}
 
 template <typename T, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs a) {
@@ -72,34 +86,50 @@ __global__ __launch_bounds__(kThreads) void demap_batched_kernel(const BatchArgs
                 gsum = msum = 0.0;
                 cur = inst;
             }
-            float g = 0.0f, mi = 0.0f;
-            bool active;
-            if (kind == kKindMfma) {
-                const int64_t n = it.n0 + wave * 32 + (lane & 31);
-                active = n < b.N;
-                float y[8];
-                load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
-                bool bad = false;
-                const Frags<T, S> bfr = build_symbol_frags<T, 8, SPLIT>(y, b.c, b.K, h, bad);
-                const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
-                MfmaAcc A;
-                A.init();
-                mfma_tiles<T, 8, SPLIT>(lds_raw, lane, 0, b.M >> 5, b.m, bfr, A);
-                mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, txl, lane, g, mi);
-            } else {
-                const int64_t n = it.n0 + tid;
-                active = n < b.N;
-                float y[8];
-                load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
-                DM_VALU_ACC_DECL
-                const int Mpad = b.M < 16 ? 16 : b.M;
-                valu_accumulate<8>(reinterpret_cast<const float*>(lds_raw), 0, Mpad, y, b.c, b.K, b.m, accA, accB,
-                                   hi0, hi1);
-                valu_epilogue<8>(b, k, n, active, y, accA, accB, hi0, hi1, g, mi);
+            // The item's sub symbol tiles; GMI / MI terms summed per lane, then over the wave once.
+            double gl = 0.0, ml = 0.0;
+            for (int sb = 0; sb < d.sub; ++sb) {
+                float g = 0.0f, mi = 0.0f;
+                bool active;
+                if (kind == kKindMfma) {
+                    const int64_t n = it.n0 + (int64_t)sb * (kWaves * 32) + wave * 32 + (lane & 31);
+                    active = n < b.N;
+                    float y[8];
+                    load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
+                    bool bad = false;
+                    const Frags<T, S> bfr = build_symbol_frags<T, 8, SPLIT>(y, b.c, b.K, h, bad);
+                    const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
+                    switch (b.M) {  // uniform: 32..256 points take the compile-time tile loop
+                        case 32: small_item<T, SPLIT, 1>(lds_raw, b, k, d.pv, bfr, n, active, bad, txl, lane, g, mi); break;
+                        case 64: small_item<T, SPLIT, 2>(lds_raw, b, k, d.pv, bfr, n, active, bad, txl, lane, g, mi); break;
+                        case 128: small_item<T, SPLIT, 4>(lds_raw, b, k, d.pv, bfr, n, active, bad, txl, lane, g, mi); break;
+                        case 256: small_item<T, SPLIT, 8>(lds_raw, b, k, d.pv, bfr, n, active, bad, txl, lane, g, mi); break;
+                        default: {
+                            MfmaAcc A;
+                            A.init();
+                            mfma_tiles<T, 8, SPLIT>(lds_raw, lane, 0, b.M >> 5, b.m, bfr, A);
+                            mfma_epilogue<T, 8, SPLIT>(b, k, d.pv, bfr, A, n, active, bad, txl, lane, g, mi);
+                        }
+                    }
+                } else {
+                    const int64_t n = it.n0 + (int64_t)sb * kThreads + tid;
+                    active = n < b.N;
+                    float y[8];
+                    load_symbol<8>(y, b.y + (size_t)(active ? n : 0) * b.D, b.D, active);
+                    DM_VALU_ACC_DECL
+                    const int Mpad = b.M < 16 ? 16 : b.M;
+                    valu_accumulate<8>(reinterpret_cast<const float*>(lds_raw), 0, Mpad, y, b.c, b.K, b.m, accA, accB,
+                                       hi0, hi1);
+                    valu_epilogue<8>(b, k, n, active, y, accA, accB, hi0, hi1, g, mi);
+                }
+                if (active) {
+                    gl += (double)g;
+                    ml += (double)mi;
+                }
             }
             if (k.acc) {
-                gsum += wave_sum(active ? (double)g : 0.0);
-                msum += wave_sum(active ? (double)mi : 0.0);
+                gsum += wave_sum(gl);
+                msum += wave_sum(ml);
             }
         }
         if (cur >= 0 && k.acc && lane == 0) {

@@ -1,7 +1,14 @@
 // Batched demapping plans: one persistent launch over many instances of uneven M, D and N,
-// an autotuner that picks the kernel body per (M, D, precision) class by timing, a work list
-// that workgroups claim chunk by chunk from a device counter at run time, and a hipGraph that
-// replays zero-fill + batched kernel + fix-up with one launch.
+// an autotuner that picks the launch shape by timing, a work list that workgroups claim chunk
+// by chunk from a device counter at run time, and a hipGraph that replays zero-fill + batched
+// kernel + fix-up with one launch.
+//
+// Shape of a plan: per (M, D, precision) class the kernel body (FP32 direct differences or MFMA
+// cross terms) and the work-item size (1, 2 or 4 of the body's symbol tiles: larger items pay
+// the per-item descriptor reads and wave reductions less often, smaller ones balance the tail
+// better); per plan the claim size (1, 2, 4 or 8 work items per counter increment).  The
+// autotuner times every body x item size of a class on a replicated probe block large enough
+// to fill the GPU (cached per GPU arch), then the whole plan at each claim size.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,13 +33,16 @@ using namespace dmapi;
 
 namespace {
 
-constexpr int kProbeSymbols = 32768;  // symbols timed per autotune candidate
-constexpr int kGrab = 4;              // work items per claim of a workgroup
+constexpr int kGrabDefault = 4;       // work items per claim without autotuning
+constexpr int kSubs[] = {1, 2, 4};    // item sizes (symbol tiles per work item) tried per class
+constexpr int kGrabs[] = {1, 2, 4, 8};  // claim sizes tried per plan
+constexpr int kProbeItemsPerCu = 4;   // probe block: this many work items per CU
+constexpr int kProbeCopies = 64;      // at most this many copies of the probe instance
 
 struct TuneKey {
-    int M, D, prec, kind;
+    int M, D, prec, kind, sub;
     bool operator<(const TuneKey& o) const {
-        return std::tie(M, D, prec, kind) < std::tie(o.M, o.D, o.prec, o.kind);
+        return std::tie(M, D, prec, kind, sub) < std::tie(o.M, o.D, o.prec, o.kind, o.sub);
     }
 };
 
@@ -54,18 +64,24 @@ std::string arch_name() {
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
-// Cache file: one line per entry, "arch M D prec kind ns_per_pair".
+// Cache file: one line per entry, "shape2 arch M D prec kind sub ns_per_pair" (lines of any
+// other format are ignored).
 void load_tune_cache() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
     const std::string path = tune_cache_path();
     if (path.empty()) return;
     std::ifstream f(path);
-    std::string arch = arch_name(), a;
-    TuneKey k;
-    double v;
-    while (f >> a >> k.M >> k.D >> k.prec >> k.kind >> v)
-        if (a == arch && v > 0.0) g_tune[k] = v;
+    const std::string arch = arch_name();
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string tag, a;
+        TuneKey k;
+        double v;
+        if (in >> tag >> a >> k.M >> k.D >> k.prec >> k.kind >> k.sub >> v && tag == "shape2" && a == arch && v > 0.0)
+            g_tune[k] = v;
+    }
 }
 
 void save_tune_cache() {
@@ -74,8 +90,8 @@ void save_tune_cache() {
     std::ofstream f(path, std::ios::trunc);
     const std::string arch = arch_name();
     for (const auto& kv : g_tune)
-        f << arch << ' ' << kv.first.M << ' ' << kv.first.D << ' ' << kv.first.prec << ' ' << kv.first.kind << ' '
-          << kv.second << '\n';
+        f << "shape2 " << arch << ' ' << kv.first.M << ' ' << kv.first.D << ' ' << kv.first.prec << ' '
+          << kv.first.kind << ' ' << kv.first.sub << ' ' << kv.second << '\n';
 }
 
 bool mfma_possible(const dm_constellation* c, int prec) {
@@ -88,9 +104,10 @@ bool mfma_possible(const dm_constellation* c, int prec) {
 }  // namespace
 
 struct dm_plan {
-    int n_inst = 0, prec = 0, grid = 0, fix_grid = 0, device = 0;
+    int n_inst = 0, prec = 0, grid = 0, fix_grid = 0, device = 0, grab = 0;
     std::vector<dm_instance> inst;
     std::vector<int> kind;
+    std::vector<int> sub;  // symbol tiles per work item
     std::vector<double> ns_per_pair;
     dm::BatchDesc* d_desc = nullptr;
     dm::WorkItem* d_items = nullptr;
@@ -132,6 +149,7 @@ int build_descs(dm_plan* p, std::vector<dm::BatchDesc>& desc) {
         d.view.want_llr = in.llr ? 1 : 0;
         d.view.tag = i;
         d.kind = p->kind[i];
+        d.sub = p->sub[i];
         if (d.kind == dm::kKindMfma) {
             r = ensure_frag(c, p->prec, true);
             if (r) return r;
@@ -153,7 +171,7 @@ void build_work(const dm_plan* p, std::vector<dm::WorkItem>& items) {
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     for (int i : order) {
-        const int tile = dm::batched_tile_symbols(p->kind[i]);
+        const int64_t tile = (int64_t)dm::batched_tile_symbols(p->kind[i]) * p->sub[i];
         for (int64_t n0 = 0; n0 < p->inst[i].N; n0 += tile) items.push_back(dm::WorkItem{i, 0, n0});
     }
 }
@@ -176,7 +194,7 @@ int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const
     p->args.desc = p->d_desc;
     p->args.items = p->d_items;
     p->args.n_items = (int32_t)items.size();
-    p->args.grab = kGrab;
+    p->args.grab = p->grab;
     p->args.next = tail + p->n_inst + 2;
     p->args.sinks.acc = acc;
     p->args.sinks.fix_pairs = tail;
@@ -207,15 +225,19 @@ void free_plan(dm_plan* p) {
     delete p;
 }
 
-// Plan skeleton without graph: validated instances, kinds and per-pair costs set by caller.
+// Plan skeleton without graph: validated instances, kinds, item sizes, per-pair costs and
+// claim size set by the caller.
 int make_plan(const dm_instance* inst, int n_inst, int prec, const std::vector<int>& kinds,
-              const std::vector<double>& cost, int grid_cap, dm_plan** out) {
+              const std::vector<int>& subs, const std::vector<double>& cost, int grab, int grid_cap,
+              dm_plan** out) {
     auto* p = new (std::nothrow) dm_plan();
     if (!p) return fail(DM_ENOMEM, "host allocation failed");
     p->n_inst = n_inst;
     p->prec = prec;
+    p->grab = grab;
     p->inst.assign(inst, inst + n_inst);
     p->kind = kinds;
+    p->sub = subs;
     p->ns_per_pair = cost;
     int cus = 0;
     hipError_t e = hipGetDevice(&p->device);
@@ -275,20 +297,15 @@ int validate_instances(const dm_instance* inst, int n_inst, int prec) {
     return DM_OK;
 }
 
-// Time one instance class with one kind on the first kProbeSymbols symbols of its block.
-int time_candidate(const dm_instance& in, int prec, int kind, double* ns_per_pair) {
-    dm_instance probe = in;
-    probe.N = std::min<int64_t>(in.N, kProbeSymbols);
-    probe.llr = nullptr;  // timing run writes no LLRs
-    dm_plan* p = nullptr;
-    int r = make_plan(&probe, 1, prec, std::vector<int>{kind}, std::vector<double>{1.0}, 0, &p);
-    if (r) return r;
+// Best time (ms) of two launches after one warm-up launch of a plan on a private stream.
+int time_plan(dm_plan* p, float* best_ms) {
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best = 1e30f;
+    int r = DM_OK;
     for (int rep = 0; e == hipSuccess && rep < 3; ++rep) {
         (void)hipEventRecord(e0, st);
         if ((r = enqueue(p, st))) break;
@@ -296,15 +313,35 @@ int time_candidate(const dm_instance& in, int prec, int kind, double* ns_per_pai
         e = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) best = std::min(best, ms);  // first run warms up
+        if (rep > 0) best = std::min(best, ms);  // the first launch warms up
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st) (void)hipStreamDestroy(st);
-    free_plan(p);
     if (r) return r;
     if (e != hipSuccess) return hip_fail(e, "autotune timing");
-    *ns_per_pair = (double)best * 1e6 / ((double)std::max<int64_t>(probe.N, 1) * in.c->M);
+    *best_ms = best;
+    return DM_OK;
+}
+
+// Time one class with one shape (kind, item size) on a probe block of about kProbeItemsPerCu
+// work items per CU: copies of the instance's first symbols (read only, no LLRs written).
+int time_candidate(const dm_instance& in, int prec, int kind, int sub, int cus, double* ns_per_pair) {
+    const int64_t want = (int64_t)kProbeItemsPerCu * cus * dm::batched_tile_symbols(kind) * sub;
+    dm_instance probe = in;
+    probe.N = std::min<int64_t>(in.N, want);
+    probe.llr = nullptr;
+    const int copies = (int)std::min<int64_t>(kProbeCopies, (want + probe.N - 1) / std::max<int64_t>(probe.N, 1));
+    std::vector<dm_instance> insts(copies, probe);
+    dm_plan* p = nullptr;
+    int r = make_plan(insts.data(), copies, prec, std::vector<int>(copies, kind), std::vector<int>(copies, sub),
+                      std::vector<double>(copies, 1.0), kGrabDefault, 0, &p);
+    if (r) return r;
+    float ms = 0.0f;
+    r = time_plan(p, &ms);
+    free_plan(p);
+    if (r) return r;
+    *ns_per_pair = (double)ms * 1e6 / ((double)std::max<int64_t>(probe.N, 1) * copies * in.c->M);
     return DM_OK;
 }
 
@@ -317,7 +354,13 @@ int dm_plan_create(const dm_instance* inst, int n_inst, int prec, int flags, dm_
     *out = nullptr;
     int r = validate_instances(inst, n_inst, prec);
     if (r) return r;
-    std::vector<int> kinds(n_inst);
+    const int force_items = (flags >> 8) & 0xF, force_claim = (flags >> 12) & 0xF;
+    if (force_items > 3) return fail(DM_EINVAL, "DM_PLAN_ITEMS(k) needs k in 1..3");
+    if (force_claim > 4) return fail(DM_EINVAL, "DM_PLAN_CLAIM(k) needs k in 1..4");
+    int cus = 0, dev = 0;
+    DM_HIP_TRY(hipGetDevice(&dev));
+    DM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<int> kinds(n_inst), subs(n_inst, force_items ? 1 << (force_items - 1) : 1);
     std::vector<double> cost(n_inst, 0.0);
     for (int i = 0; i < n_inst; ++i) {
         const dm_constellation* c = inst[i].c;
@@ -333,7 +376,8 @@ int dm_plan_create(const dm_instance* inst, int n_inst, int prec, int flags, dm_
         // Default cost model: measured-order-of-magnitude ns per pair of each body.
         cost[i] = kinds[i] == dm::kKindMfma ? 1.6e-4 : 5.0e-4;
     }
-    if ((flags & DM_PLAN_AUTOTUNE) && !(flags & (DM_PLAN_FORCE_VALU | DM_PLAN_FORCE_MFMA))) {
+    const bool tune = (flags & DM_PLAN_AUTOTUNE) != 0;
+    if (tune) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         load_tune_cache();
         bool tuned = false;
@@ -341,32 +385,58 @@ int dm_plan_create(const dm_instance* inst, int n_inst, int prec, int flags, dm_
             const dm_constellation* c = inst[i].c;
             if (inst[i].N == 0) continue;
             double best = 0.0;
-            int best_kind = dm::kKindValu;
+            int best_kind = kinds[i], best_sub = subs[i];
             for (int kind = dm::kKindValu; kind <= dm::kKindMfma; ++kind) {
                 if (kind == dm::kKindMfma && !mfma_possible(c, prec)) continue;
-                const TuneKey key{c->M, c->D, prec, kind};
-                auto it = g_tune.find(key);
-                double ns;
-                if (it != g_tune.end()) {
-                    ns = it->second;
-                } else {
-                    r = time_candidate(inst[i], prec, kind, &ns);
-                    if (r) return r;
-                    g_tune[key] = ns;
-                    tuned = true;
-                }
-                if (best == 0.0 || ns < best) {
-                    best = ns;
-                    best_kind = kind;
+                if ((flags & DM_PLAN_FORCE_VALU) && kind != dm::kKindValu) continue;
+                if ((flags & DM_PLAN_FORCE_MFMA) && kind != dm::kKindMfma) continue;
+                for (int sub : kSubs) {
+                    if (force_items && sub != subs[i]) continue;
+                    const TuneKey key{c->M, c->D, prec, kind, sub};
+                    auto it = g_tune.find(key);
+                    double ns;
+                    if (it != g_tune.end()) {
+                        ns = it->second;
+                    } else {
+                        r = time_candidate(inst[i], prec, kind, sub, cus, &ns);
+                        if (r) return r;
+                        g_tune[key] = ns;
+                        tuned = true;
+                    }
+                    if (best == 0.0 || ns < best) {
+                        best = ns;
+                        best_kind = kind;
+                        best_sub = sub;
+                    }
                 }
             }
             kinds[i] = best_kind;
+            subs[i] = best_sub;
             cost[i] = best;
         }
         if (tuned) save_tune_cache();
     }
+    // Claim size: forced, the default, or the fastest whole plan (timed without LLR writes).
+    int grab = force_claim ? 1 << (force_claim - 1) : kGrabDefault;
+    if (tune && !force_claim) {
+        std::vector<dm_instance> quiet(inst, inst + n_inst);
+        for (auto& q : quiet) q.llr = nullptr;
+        float best_ms = 0.0f;
+        for (int g : kGrabs) {
+            dm_plan* tp = nullptr;
+            if ((r = make_plan(quiet.data(), n_inst, prec, kinds, subs, cost, g, 0, &tp))) return r;
+            float ms = 0.0f;
+            r = time_plan(tp, &ms);
+            free_plan(tp);
+            if (r) return r;
+            if (best_ms == 0.0f || ms < best_ms) {
+                best_ms = ms;
+                grab = g;
+            }
+        }
+    }
     dm_plan* p = nullptr;
-    r = make_plan(inst, n_inst, prec, kinds, cost, 0, &p);
+    r = make_plan(inst, n_inst, prec, kinds, subs, cost, grab, 0, &p);
     if (r) return r;
     // Capture zero-fill + batched kernel + fix-up into a graph on a private stream.
     hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
@@ -416,11 +486,12 @@ int dm_plan_results(dm_plan* p, double* gmi, double* mi, int64_t* fixup_pairs, v
     return DM_OK;
 }
 
-int dm_plan_info(const dm_plan* p, int* kinds, double* ns_per_pair) {
+int dm_plan_info(const dm_plan* p, int* kinds, double* ns_per_pair, int32_t* item_symbols) {
     if (!p) return fail(DM_EINVAL, "null plan");
     for (int i = 0; i < p->n_inst; ++i) {
         if (kinds) kinds[i] = p->kind[i];
         if (ns_per_pair) ns_per_pair[i] = p->ns_per_pair[i];
+        if (item_symbols) item_symbols[i] = dm::batched_tile_symbols(p->kind[i]) * p->sub[i];
     }
     return DM_OK;
 }

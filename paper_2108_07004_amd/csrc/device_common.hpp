@@ -93,7 +93,7 @@ struct BatchDesc {             // one instance (device memory); view.tag = insta
     const uint4* frag;         // MFMA point operands, fragment order (D padded to 8), or null
     const uint16_t* pv;        // the same operands per label, or null
     int32_t kind;
-    int32_t pad;
+    int32_t sub;               // symbol tiles per work item (work item = sub x the body's tile)
 };
 
 struct WorkItem {              // symbols [n0, n0 + tile) of one instance

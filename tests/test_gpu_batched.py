@@ -47,7 +47,7 @@ def test_batched_plan_matches_oracle_per_instance():
     insts = _small_instances()
     items, host, _ = _build(insts)
     plan = dm.Plan(items, prec="fp16x3", autotune=True)
-    kinds, ns = plan.info()
+    kinds, ns, _ = plan.info()
     assert set(kinds.tolist()) <= {0, 1} and np.all(ns > 0)
     plan.launch()
     gmi, mi, fx = plan.results()
@@ -76,6 +76,51 @@ def test_forced_bodies_agree():
     for i, (inst, y, tx) in enumerate(host):
         ref = oracle.demap(inst.const.points, inst.const.labels, inst.sigma2, y, tx, llr=False)
         assert abs(gv[i] - ref["gmi"]) <= GMI_TOL
+
+
+@pytest.mark.parametrize("body", ["valu", "mfma"])
+def test_forced_shapes_agree_with_oracle(body):
+    """Two work-item sizes and two claim sizes per kernel body: LLRs bit-identical across
+    shapes (per-symbol work does not depend on the partition), GMI / MI against the oracle."""
+    import torch
+    insts = [i for i in W.batched_instances(64, n_lo=12, n_hi=15) if i.const.M >= 32][:12]
+    items, host, _ = _build(insts)
+    ref_llr, ref_g = None, None
+    for tiles, claim in ((1, 1), (4, 8), (2, 4)):
+        plan = dm.Plan(items, prec="fp16x3", autotune=False, force=body, item_tiles=tiles, claim=claim)
+        kinds, _, sym = plan.info()
+        n_items, grab, _ = plan.stats()
+        base = 1024 if body == "valu" else 512
+        assert np.all(kinds == (0 if body == "valu" else 1)) and np.all(sym == base * tiles) and grab == claim
+        for it in items:
+            it[4].fill_(float("nan"))
+        plan.launch()
+        g, m, _ = plan.results()
+        torch.cuda.synchronize()
+        llrs = [it[4].clone() for it in items]
+        if ref_llr is None:
+            ref_llr, ref_g = llrs, g
+            for i, (inst, y, tx) in enumerate(host):
+                ref = oracle.demap(inst.const.points, inst.const.labels, inst.sigma2, y, tx)
+                tol = LLR_TOL_FP32 if body == "valu" else LLR_TOL_MFMA_FP16X3
+                assert rel_err(llrs[i].cpu().numpy(), ref["llr"]) <= tol, (body, i)
+                assert abs(g[i] - ref["gmi"]) <= GMI_TOL and abs(m[i] - ref["mi_mean"]) <= GMI_TOL, (body, i)
+        else:
+            for a, b in zip(ref_llr, llrs):
+                assert torch.equal(a, b), (body, tiles, claim)
+            assert np.max(np.abs(g - ref_g)) <= 1e-6, (body, tiles, claim)
+
+
+def test_autotuned_shape_is_reported():
+    insts = [i for i in W.batched_instances(64, n_lo=12, n_hi=14)][:10]
+    items, _, _ = _build(insts, with_llr=False)
+    plan = dm.Plan(items, prec="fp16x3", autotune=True)
+    kinds, ns, sym = plan.info()
+    _, grab, _ = plan.stats()
+    assert grab in (1, 2, 4, 8) and np.all(ns > 0)
+    for k, s_ in zip(kinds, sym):
+        base = 1024 if k == 0 else 512
+        assert s_ in (base, 2 * base, 4 * base)
 
 
 def test_graph_replays_interleaved_with_eager_work():
@@ -141,7 +186,7 @@ def test_fixups_of_instances_beyond_the_lds_tag_table():
         insts.append(W.Instance(i, W.gaussian_constellation(M, D, 3, i), 700 + 37 * k, snr))
     items, host, _ = _build(insts)
     plan = dm.Plan(items, prec="fp16x3", autotune=True)
-    kinds, _ = plan.info()
+    kinds, _, _ = plan.info()
     plan.launch()
     gmi, mi, fx = plan.results()
     torch.cuda.synchronize()

@@ -170,7 +170,7 @@ def test_batched_plan_with_many_claims_per_workgroup():
     insts = W.batched_instances(64, n_lo=14, n_hi=17)
     items, host = _plan_items(insts)
     plan = dm.Plan(items, prec="fp16x3", autotune=True)
-    kinds, ns = plan.info()
+    kinds, ns, _ = plan.info()
     n_items, grab, grid = plan.stats()
     _say(f"plan: {sum(i.N for i in insts)} symbols, {n_items} work items, claims of {grab}, {grid} workgroups")
     assert n_items >= 4 * grab * grid, (n_items, grab, grid)  # every workgroup claims several chunks
@@ -192,7 +192,7 @@ def test_benchmark_plan_matches_single_instance_path_and_sampled_oracle():
     insts = W.batched_instances()
     items, host = _plan_items(insts)
     plan = dm.Plan(items, prec="fp16x3", autotune=True)
-    kinds, _ = plan.info()
+    kinds, _, _ = plan.info()
     plan.launch()
     gmi, mi, fx = plan.results()
     torch.cuda.synchronize()
