@@ -15,8 +15,19 @@ struct FixEntry {
     uint32_t n;     // symbol index within its block
     uint32_t tag;   // block (SNR point or instance) the symbol belongs to
     uint32_t mask;  // bit p set: recompute label bit p; kMiFlag: recompute the MI term
-    uint32_t pad;
+    uint32_t near;  // bits of log2 of the symbol's total sum (t units) when that total is at least
+                    // 2^(m-78) and finite (kNearNone otherwise): then a flagged bit's near subset
+                    // holds all of it to FP32 precision, and only its far subset needs recomputing
 };
+constexpr uint32_t kNearNone = 0x7FC00000u;  // quiet NaN: no near-subset log-sum passed
+
+// The FixEntry.near word for a symbol total stot (the demapper's own sum of all M terms).
+__device__ __forceinline__ uint32_t near_word(float stot, int m, bool bad) {
+    if (bad || !(stot >= __builtin_ldexpf(1.0f, m - 78)) || !(stot < 3.0e38f)) return kNearNone;
+    const int e = __builtin_amdgcn_frexp_expf(stot);
+    const float l = (float)e + __builtin_amdgcn_logf(__builtin_amdgcn_frexp_mantf(stot));
+    return __builtin_bit_cast(uint32_t, l);
+}
 
 // One received block: a constellation at one noise level with its data.
 struct BlockView {
@@ -403,10 +414,15 @@ __device__ __forceinline__ float row_reduce_f(float v, Op op) {
 // Row fix-up for a constellation of M = 16 * NPL points (M = 128 or 256, the same for every
 // queued symbol): each 16-lane row of a wavefront takes one queued symbol, so a wavefront
 // recomputes four at once.  Lane r of a row keeps the exponents t = K - c ||y - x_j||^2 of labels
-// j = r + 16 q in registers; label bits 0-3 of j are bits of r, bits 4 and up bits of q.  Each
-// flagged bit is the same two-pass subset log-sum-exp as wave_exact_llr2 (subset maxima, then
-// the exp2 sums under them), reduced over the row.  Lane 0 of the row writes the LLR and
-// accumulates the GMI / MI corrections, which add(tag, slot, which, value) receives.
+// j = r + 16 q in registers; label bits 0-3 of j are bits of r, bits 4 and up bits of q.  The bit
+// loop is unrolled, so every subset split is known at compile time: for p < 4 a lane's 16 values
+// all lie in one subset, for p >= 4 the registers split in halves.  Each flagged bit first takes
+// both subset maxima (row reductions).  When the queue entry carries the near-subset log-sum
+// (FixEntry.near), only the far subset -- the one with the smaller maximum -- is summed under
+// its maximum and L = (far log-sum) - (near log-sum) with the sign of the far bit; otherwise
+// both subsets are summed under their own maxima (the two-pass log-sum-exp of
+// wave_exact_llr2).  Lane 0 of the row writes the LLR and accumulates the GMI / MI
+// corrections, which add(tag, slot, which, value) receives.
 template <int DP, int NPL, typename ViewFn, typename AddFn>
 __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count) {
     constexpr int m = NPL == 8 ? 7 : 8;
@@ -423,6 +439,8 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count)
         const bool live = i < count;
         const FixEntry e = k.queue[live ? i : base];  // a spare row repeats a valid entry, masked off
         const uint32_t mask = live ? e.mask : 0u;
+        const float near_lse = __builtin_bit_cast(float, e.near);
+        const bool has_near = e.near != kNearNone;
         const BlockView b = view(e);
         float y[DP];
         load_symbol<DP>(y, b.y + (size_t)e.n * b.D, b.D, true);
@@ -432,24 +450,73 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count)
         for (int q = 0; q < NPL; ++q) t[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K);
         double gc = 0.0, mc = 0.0;
         // p = 0 .. m-1: label bits; p = m: the MI term (every point in subset 0).
+#pragma unroll
         for (int p = 0; p <= m; ++p) {
             const bool want = p < m ? ((mask >> p) & 1u) != 0u : ((mask & kMiFlag) != 0u && b.tx != nullptr);
             if (__ballot(want) == 0ull) continue;
+            // subset maxima
             float mx0 = -INFINITY, mx1 = -INFINITY;
+            if (p < 4) {
+                float mxl = t[0];
 #pragma unroll
-            for (int q = 0; q < NPL; ++q) {
-                const bool one = p < 4 ? ((r >> p) & 1) != 0 : (p < m && ((q >> (p - 4)) & 1) != 0);
-                if (one) mx1 = fmaxf(mx1, t[q]);
-                else mx0 = fmaxf(mx0, t[q]);
+                for (int q = 1; q < NPL; ++q) mxl = fmaxf(mxl, t[q]);
+                const bool one = ((r >> p) & 1) != 0;
+                mx0 = one ? -INFINITY : mxl;
+                mx1 = one ? mxl : -INFINITY;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) {
+                    if (p < m && ((q >> (p - 4)) & 1)) mx1 = fmaxf(mx1, t[q]);
+                    else mx0 = fmaxf(mx0, t[q]);
+                }
             }
             mx0 = row_reduce_f(mx0, fmax2);
             mx1 = row_reduce_f(mx1, fmax2);
+            // far-only when every row of the wave that wants this bit passed its near log-sum
+            const bool far_only = p < m && __ballot(want && !has_near) == 0ull;
             float s0 = 0.0f, s1 = 0.0f;
+            if (far_only) {
+                const int fb = mx1 < mx0 ? 1 : 0;  // the far subset: the smaller maximum
+                const float mxf = fb ? mx1 : mx0;
+                float sf = 0.0f;
+                if (p < 4) {
+                    if (((r >> p) & 1) == fb) {
 #pragma unroll
-            for (int q = 0; q < NPL; ++q) {
-                const bool one = p < 4 ? ((r >> p) & 1) != 0 : (p < m && ((q >> (p - 4)) & 1) != 0);
-                if (one) s1 += hw_exp2(t[q] - mx1);
-                else s0 += hw_exp2(t[q] - mx0);
+                        for (int q = 0; q < NPL; ++q) sf += hw_exp2(t[q] - mxf);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q) {
+                        if (((q >> (p - 4)) & 1) == 0) {  // pair q with q | (1 << (p-4)); take the far one
+                            const float v = fb ? t[q | (1 << (p - 4))] : t[q];
+                            sf += hw_exp2(v - mxf);
+                        }
+                    }
+                }
+                sf = row_reduce_f(sf, fadd2);
+                if (want && r == 0) {
+                    // L = log2 S1 - log2 S0 with the far subset's log-sum exact and the near one passed
+                    const float lf = mxf + hw_log2(sf);
+                    const float L = fb ? lf - near_lse : near_lse - lf;
+                    if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
+                    if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
+                }
+                continue;
+            }
+            if (p < 4) {
+                const bool one = ((r >> p) & 1) != 0;
+                const float sh = one ? mx1 : mx0;
+                float sl = 0.0f;
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) sl += hw_exp2(t[q] - sh);
+                s0 = one ? 0.0f : sl;
+                s1 = one ? sl : 0.0f;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) {
+                    if (p < m && ((q >> (p - 4)) & 1)) s1 += hw_exp2(t[q] - mx1);
+                    else s0 += hw_exp2(t[q] - mx0);
+                }
             }
             s0 = row_reduce_f(s0, fadd2);
             s1 = row_reduce_f(s1, fadd2);
@@ -540,14 +607,15 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
     }
 }
 
-// Queue a symbol for the fix-up; when the queue is full the calling lane recomputes it in
-// place (slow but exact) and the corrections come back through gc / mc.
+// Queue a symbol for the fix-up (near: FixEntry.near of the symbol); when the queue is full the
+// calling lane recomputes it in place (slow but exact) and the corrections come back through
+// gc / mc.
 template <int DP>
 __device__ __forceinline__ void queue_or_fix(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask,
-                                             double& gc, double& mc) {
+                                             uint32_t near, double& gc, double& mc) {
     if (k.fix_pairs) atomicAdd(k.fix_pairs + b.tag, (uint32_t)__popc(mask & 0xFFFFu));
     const uint32_t slot = atomicAdd(k.queue_count, 1u);
-    if (slot < k.queue_cap) k.queue[slot] = FixEntry{n, (uint32_t)b.tag, mask, 0u};
+    if (slot < k.queue_cap) k.queue[slot] = FixEntry{n, (uint32_t)b.tag, mask, near};
     else fixup_one<DP>(b, k, n, mask, gc, mc);
 }
 

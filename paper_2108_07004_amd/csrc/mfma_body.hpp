@@ -418,7 +418,7 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
     mask = half_or(mask);
     if (mask && active && h == 0) {
         double gc = 0.0, mc = 0.0;
-        queue_or_fix<D>(b, k, (uint32_t)n, mask, gc, mc);
+        queue_or_fix<D>(b, k, (uint32_t)n, mask, near_word(stot, m, bad_sym), gc, mc);
         g += (float)gc;
         mi += (float)mc;
     }

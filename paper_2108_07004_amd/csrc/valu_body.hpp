@@ -116,7 +116,7 @@ __device__ __forceinline__ void valu_epilogue(const BlockView& b, const Sinks& k
     }
     if (mask && active) {
         double gc = 0.0, mc = 0.0;
-        queue_or_fix<DP>(b, k, (uint32_t)n, mask, gc, mc);
+        queue_or_fix<DP>(b, k, (uint32_t)n, mask, near_word(stot, m, false), gc, mc);
         g += (float)gc;
         mi += (float)mc;
     }
