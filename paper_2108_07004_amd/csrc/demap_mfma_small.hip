@@ -44,8 +44,22 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
     };
     int s_idx = (int)(blockIdx.x / blks_per_snr);
     int64_t r = blockIdx.x - (int64_t)s_idx * blks_per_snr;
+    // The received symbols and transmitted rows of the next batch are loaded one batch ahead:
+    // their latency overlaps the current batch's tile loop and epilogue.
+    const int sub = wave * 32 + (lane & 31);
+    auto fetch = [&](int s, int64_t rr, float (&yy)[D], uint32_t& row) {
+        const int64_t n = rr * sym_per_blk + sub;
+        const bool act = n < a.N;
+        const float* yrow = a.snr[s].y + (size_t)(act ? n : 0) * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) yy[d] = yrow[d];
+        row = (a.tx && act) ? (uint32_t)a.tx[n] : 0u;
+    };
+    float y_nx[D];
+    uint32_t row_nx = 0;
+    if ((int64_t)blockIdx.x < total) fetch(s_idx, r, y_nx, row_nx);
     for (int64_t bt = blockIdx.x; bt < total; bt += gridDim.x) {
-        const int64_t n = r * sym_per_blk + wave * 32 + (lane & 31);
+        const int64_t n = r * sym_per_blk + sub;
         if (s_idx != cur) {
             if (cur >= 0 && k.acc) flush();
             gsum = msum = 0.0;
@@ -53,16 +67,27 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
         }
         const bool active = n < a.N;
         const BlockView b = view_sym(a, s_idx, n, active);
-        const float* yrow = b.y + (size_t)(active ? n : 0) * D;
         float y[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const float v = yrow[d];
-            y[d] = active ? v : 0.0f;
+        for (int d = 0; d < D; ++d) y[d] = active ? y_nx[d] : 0.0f;
+        uint32_t row = row_nx;
+        // next batch: advance (s_idx, r) and issue its loads
+        r += gridDim.x;
+        while (r >= blks_per_snr) {
+            r -= blks_per_snr;
+            ++s_idx;
+        }
+        if (bt + gridDim.x < total) fetch(s_idx, r, y_nx, row_nx);
+        int txl = 0;
+        if (b.tx && active) {
+            if (row >= (uint32_t)b.M) {  // out-of-range row: clamped and reported
+                if (k.bad_tx) atomicOr(k.bad_tx, 1u);
+                row = 0;
+            }
+            txl = (int)b.row2label[row];
         }
         bool bad = false;
         const Frags<T, S> bfr = build_symbol_frags<T, D, SPLIT>(y, b.c, b.K, h, bad);
-        const int txl = (b.tx && active) ? tx_label(b, k, n) : 0;
 
         float S0[MB], S1[MB], tot;
         mfma_small_sums<T, D, SPLIT, NT>(lds_frag, lane, bfr, S0, S1, tot);
@@ -71,11 +96,6 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
         if (k.acc && active) {
             gsum += (double)g;
             msum += (double)mi;
-        }
-        r += gridDim.x;
-        while (r >= blks_per_snr) {
-            r -= blks_per_snr;
-            ++s_idx;
         }
     }
     if (cur >= 0 && k.acc) flush();
