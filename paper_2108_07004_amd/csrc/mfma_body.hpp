@@ -425,15 +425,39 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
 }
 
 
-// The generic epilogue: subset sums from the accumulators, then mfma_finish over b.m bits.
+// Subset sums of the first MB label bits and mfma_finish with MB bits known at compile time
+// (MB == 16: b.m bits at run time).
+template <typename T, int D, bool SPLIT, int MB>
+__device__ __forceinline__ void mfma_epilogue_m(const BlockView& b, const Sinks& k, const uint16_t* pv,
+                                                const Frags<T, Slots<D, SPLIT>::S>& bfr, const MfmaAcc& A,
+                                                int64_t n, bool active, bool bad, int txl, int lane, float& g,
+                                                float& mi) {
+    float S0a[16], S1a[16], tot;
+    mfma_subset_sums(A, lane >> 5, S0a, S1a, tot);
+    float S0[MB], S1[MB];
+#pragma unroll
+    for (int p = 0; p < MB; ++p) {
+        S0[p] = S0a[p];
+        S1[p] = S1a[p];
+    }
+    mfma_finish<T, D, SPLIT, MB>(b, k, pv, bfr, S0, S1, tot, n, active, bad, txl, lane, g, mi);
+}
+
+// The generic epilogue: subset sums from the accumulators, then mfma_finish over b.m bits; the
+// constellations of 512 to 4096 points (m = 9..12) take epilogues with m fixed at compile time
+// (no per-bit guards), the branch on m being uniform over the launch.
 template <typename T, int D, bool SPLIT>
 __device__ __forceinline__ void mfma_epilogue(const BlockView& b, const Sinks& k, const uint16_t* pv,
                                               const Frags<T, Slots<D, SPLIT>::S>& bfr, const MfmaAcc& A,
                                               int64_t n, bool active, bool bad, int txl, int lane, float& g,
                                               float& mi) {
-    float S0[16], S1[16], tot;
-    mfma_subset_sums(A, lane >> 5, S0, S1, tot);
-    mfma_finish<T, D, SPLIT, 16>(b, k, pv, bfr, S0, S1, tot, n, active, bad, txl, lane, g, mi);
+    switch (b.m) {
+        case 9: mfma_epilogue_m<T, D, SPLIT, 9>(b, k, pv, bfr, A, n, active, bad, txl, lane, g, mi); break;
+        case 10: mfma_epilogue_m<T, D, SPLIT, 10>(b, k, pv, bfr, A, n, active, bad, txl, lane, g, mi); break;
+        case 11: mfma_epilogue_m<T, D, SPLIT, 11>(b, k, pv, bfr, A, n, active, bad, txl, lane, g, mi); break;
+        case 12: mfma_epilogue_m<T, D, SPLIT, 12>(b, k, pv, bfr, A, n, active, bad, txl, lane, g, mi); break;
+        default: mfma_epilogue_m<T, D, SPLIT, 16>(b, k, pv, bfr, A, n, active, bad, txl, lane, g, mi);
+    }
 }
 
 }  // namespace dm
