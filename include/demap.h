@@ -113,9 +113,10 @@ int dm_gmi_estimate(const dm_constellation* c, int n_snr, const double* sigma2,
  *   Limits: n_snr <= 32 (DM_EINVAL beyond: the array holds 32 noise levels); any N < 2^31
  *   (a fix-up queue that fills up is recomputed in place by the demapping kernel).
  * Every call on a GPU shares that GPU's array, which keeps the last call's contents; each
- * call clears what must start at zero with a fill kernel.  Calls on one GPU are serialised
- * by a host lock held until the call has synchronised `stream`; launches that overlap the
- * array from elsewhere (another process's library copy has its own array) would race.
+ * call clears what must start at zero with a fill kernel.  Two calls whose launches overlapped
+ * on one GPU would race on the array, so calls on one GPU are serialised: a host lock is held
+ * from the first launch until the call has synchronised `stream` (each process has its own
+ * copy of the array).
  * dm_last_fixup_count reports no counts after this call (it returns DM_EINVAL).
  * Errors: as dm_gmi_estimate; DM_EUNSUPPORTED also when an operand table is missing (after
  * the points were replaced in place).
