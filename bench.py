@@ -41,10 +41,10 @@ EXP2_ISSUE_CYCLES = 2  # v_exp_f32 issues at half the full FP32 rate on gfx950 (
 # 512 MiB device copy in the same runs.  Valid only for the kernel sources they were taken on.
 TRAFFIC_PMC = {
     "prec": "fp16x3", "workload": "gauss8d2048",
-    "bytes": (4482193 * 2 + 11546636) * 1024,
+    "bytes": (4550506 * 2 + 11552808) * 1024,
     "sources": ["paper_2108_07004_amd/csrc/demap_mfma.hip", "paper_2108_07004_amd/csrc/mfma_body.hpp",
                 "paper_2108_07004_amd/csrc/device_common.hpp"],
-    "sha256": "a3fa1e593ea1d99b65845df89676ee3f3cfb630f5442cdd63663f0adeb15f717",
+    "sha256": "5b2229d3afe3cfb1b1be4ab0c94075e44921c0509d2bd4edc5960c185ff88b70",
 }
 
 
@@ -124,13 +124,20 @@ def bench_batched(prec, steps, warmup):
     pairs = float(sum(i.N * i.const.M for i in insts))
     peak = FULL_RATE / EXP2_ISSUE_CYCLES
     shapes = {}
-    for inst, k, sy in zip(insts, kinds, sym):
-        shapes[f"M{inst.const.M}/D{inst.const.D}"] = f"{'mfma' if k == 1 else 'fp32'} x {int(sy)} symbols"
+    for inst, k, sy, nsp in zip(insts, kinds, sym, ns):
+        # the class's own rate on its autotune probe block, as a fraction of the exp2 peak
+        frac = 1.0 / (nsp * 1e-9 * peak) if nsp > 0 else 0.0
+        shapes[f"M{inst.const.M}/D{inst.const.D}"] = (f"{'mfma' if k == 1 else 'fp32'} x {int(sy)} symbols, "
+                                                      f"{frac:.3f} of the exp2 peak alone")
+    # sum over instances of (probe ns per pair x pairs): the plan's time if every instance ran
+    # alone at its class's probe rate, one after the other
+    predicted_ms = float(sum(nsp * i.N * i.const.M for nsp, i in zip(ns, insts))) * 1e-6
     return {"workload": "64 instances: M in {16,64,256,1024,2048}, D in {2,4,8}, N log-uniform 2^14..2^22, "
                         "SNR U[0,20] dB, one hipGraph launch (zero-fill + persistent kernel + fix-up)",
             "symbols": n_sym, "exp2_per_launch": pairs, "ms_per_launch": ms, "symbols_per_s": n_sym / (ms * 1e-3),
             "exp2_frac_of_peak": pairs / (ms * 1e-3) / peak, "plan_create_s": t_plan,
             "fixed_shape_ms_per_launch": ms_fixed, "autotune_speedup": ms_fixed / ms,
+            "sum_of_class_probe_ms": predicted_ms,
             "shape": {"claim_items": grab, "work_items": n_items, "workgroups": grid, "per_class": shapes},
             "mfma_instances": int(np.sum(kinds == 1)), "fp32_instances": int(np.sum(kinds == 0)),
             "fixup_pairs": int(np.sum(fx)), "prec": prec}
