@@ -423,119 +423,162 @@ __device__ __forceinline__ float row_reduce_f(float v, Op op) {
 // both subsets are summed under their own maxima (the two-pass log-sum-exp of
 // wave_exact_llr2).  Lane 0 of the row writes the LLR and accumulates the GMI / MI
 // corrections, which add(tag, slot, which, value) receives.
+//
+// A wave's four rows run the bit loop for the union of their flagged bits, so the queue is taken
+// in chunks of 256 entries per workgroup (256 threads), each chunk counting-sorted by the low
+// eight mask bits in LDS before its rows are dealt out: rows of a wave then mostly share their
+// flagged bits.  The processing order does not change any result (each (symbol, bit) is written
+// once, the corrections are integer sums).
+constexpr int kFixSortChunk = 256;
+
 template <int DP, int NPL, typename ViewFn, typename AddFn>
 __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count) {
     constexpr int m = NPL == 8 ? 7 : 8;
     static_assert(NPL == 8 || NPL == 16, "row fix-up covers M = 128 and 256");
-    const int lane = threadIdx.x & 63;
+    __shared__ FixEntry s_sorted[kFixSortChunk];
+    __shared__ uint32_t s_bin[256];
+    __shared__ uint32_t s_wsum[kFixSortChunk / 64];
+    const int tid = threadIdx.x;  // blockDim.x == kFixSortChunk
+    const int lane = tid & 63;
     const int r = lane & 15;
-    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const int wv = tid >> 6;
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + wv;
     const int slot = (int)(wave % kAccSlots);
     const auto fmax2 = [](float a, float b) { return fmaxf(a, b); };
     const auto fadd2 = [](float a, float b) { return a + b; };
-    for (uint32_t base = wave * 4; base < count; base += nwaves * 4) {  // uniform over the wave
-        const uint32_t i = base + (uint32_t)(lane >> 4);
-        const bool live = i < count;
-        const FixEntry e = k.queue[live ? i : base];  // a spare row repeats a valid entry, masked off
-        const uint32_t mask = live ? e.mask : 0u;
-        const float near_lse = __builtin_bit_cast(float, e.near);
-        const bool has_near = e.near != kNearNone;
-        const BlockView b = view(e);
-        float y[DP];
-        load_symbol<DP>(y, b.y + (size_t)e.n * b.D, b.D, true);
-        const int txl = b.tx ? tx_label(b, k, e.n) : 0;
-        float t[NPL];
+    for (uint32_t c0 = blockIdx.x * kFixSortChunk; c0 < count; c0 += gridDim.x * kFixSortChunk) {  // uniform per block
+        const uint32_t nc = min((uint32_t)kFixSortChunk, count - c0);
+        // counting sort of the chunk by key = low 8 mask bits
+        s_bin[tid] = 0u;
+        __syncthreads();
+        const bool have = (uint32_t)tid < nc;
+        FixEntry mine{};
+        uint32_t key = 0u;
+        if (have) {
+            mine = k.queue[c0 + tid];
+            key = mine.mask & 0xFFu;
+            atomicAdd(&s_bin[key], 1u);
+        }
+        __syncthreads();
+        const uint32_t own = s_bin[tid];
+        uint32_t x = own;  // inclusive scan over the 256 bins: waves, then across waves
 #pragma unroll
-        for (int q = 0; q < NPL; ++q) t[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K);
-        double gc = 0.0, mc = 0.0;
-        // p = 0 .. m-1: label bits; p = m: the MI term (every point in subset 0).
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_wsum[wv] = x;
+        __syncthreads();
+        uint32_t pre = 0u;
+        for (int w = 0; w < wv; ++w) pre += s_wsum[w];
+        s_bin[tid] = x + pre - own;  // exclusive start of bin tid
+        __syncthreads();
+        if (have) s_sorted[atomicAdd(&s_bin[key], 1u)] = mine;
+        __syncthreads();
+        for (uint32_t base = (uint32_t)wv * 4; base < nc; base += (blockDim.x >> 6) * 4) {  // uniform over the wave
+            const uint32_t i = base + (uint32_t)(lane >> 4);
+            const bool live = i < nc;
+            const FixEntry e = s_sorted[live ? i : base];  // a spare row repeats a valid entry, masked off
+            const uint32_t mask = live ? e.mask : 0u;
+            const float near_lse = __builtin_bit_cast(float, e.near);
+            const bool has_near = e.near != kNearNone;
+            const BlockView b = view(e);
+            float y[DP];
+            load_symbol<DP>(y, b.y + (size_t)e.n * b.D, b.D, true);
+            const int txl = b.tx ? tx_label(b, k, e.n) : 0;
+            float t[NPL];
 #pragma unroll
-        for (int p = 0; p <= m; ++p) {
-            const bool want = p < m ? ((mask >> p) & 1u) != 0u : ((mask & kMiFlag) != 0u && b.tx != nullptr);
-            if (__ballot(want) == 0ull) continue;
-            // subset maxima
-            float mx0 = -INFINITY, mx1 = -INFINITY;
-            if (p < 4) {
-                float mxl = t[0];
+            for (int q = 0; q < NPL; ++q) t[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K);
+            double gc = 0.0, mc = 0.0;
+            // p = 0 .. m-1: label bits; p = m: the MI term (every point in subset 0).
 #pragma unroll
-                for (int q = 1; q < NPL; ++q) mxl = fmaxf(mxl, t[q]);
-                const bool one = ((r >> p) & 1) != 0;
-                mx0 = one ? -INFINITY : mxl;
-                mx1 = one ? mxl : -INFINITY;
-            } else {
-#pragma unroll
-                for (int q = 0; q < NPL; ++q) {
-                    if (p < m && ((q >> (p - 4)) & 1)) mx1 = fmaxf(mx1, t[q]);
-                    else mx0 = fmaxf(mx0, t[q]);
-                }
-            }
-            mx0 = row_reduce_f(mx0, fmax2);
-            mx1 = row_reduce_f(mx1, fmax2);
-            // far-only when every row of the wave that wants this bit passed its near log-sum
-            const bool far_only = p < m && __ballot(want && !has_near) == 0ull;
-            float s0 = 0.0f, s1 = 0.0f;
-            if (far_only) {
-                const int fb = mx1 < mx0 ? 1 : 0;  // the far subset: the smaller maximum
-                const float mxf = fb ? mx1 : mx0;
-                float sf = 0.0f;
+            for (int p = 0; p <= m; ++p) {
+                const bool want = p < m ? ((mask >> p) & 1u) != 0u : ((mask & kMiFlag) != 0u && b.tx != nullptr);
+                if (__ballot(want) == 0ull) continue;
+                // subset maxima
+                float mx0 = -INFINITY, mx1 = -INFINITY;
                 if (p < 4) {
-                    if (((r >> p) & 1) == fb) {
+                    float mxl = t[0];
 #pragma unroll
-                        for (int q = 0; q < NPL; ++q) sf += hw_exp2(t[q] - mxf);
-                    }
+                    for (int q = 1; q < NPL; ++q) mxl = fmaxf(mxl, t[q]);
+                    const bool one = ((r >> p) & 1) != 0;
+                    mx0 = one ? -INFINITY : mxl;
+                    mx1 = one ? mxl : -INFINITY;
                 } else {
 #pragma unroll
                     for (int q = 0; q < NPL; ++q) {
-                        if (((q >> (p - 4)) & 1) == 0) {  // pair q with q | (1 << (p-4)); take the far one
-                            const float v = fb ? t[q | (1 << (p - 4))] : t[q];
-                            sf += hw_exp2(v - mxf);
-                        }
+                        if (p < m && ((q >> (p - 4)) & 1)) mx1 = fmaxf(mx1, t[q]);
+                        else mx0 = fmaxf(mx0, t[q]);
                     }
                 }
-                sf = row_reduce_f(sf, fadd2);
-                if (want && r == 0) {
-                    // L = log2 S1 - log2 S0 with the far subset's log-sum exact and the near one passed
-                    const float lf = mxf + hw_log2(sf);
-                    const float L = fb ? lf - near_lse : near_lse - lf;
-                    if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
-                    if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
-                }
-                continue;
-            }
-            if (p < 4) {
-                const bool one = ((r >> p) & 1) != 0;
-                const float sh = one ? mx1 : mx0;
-                float sl = 0.0f;
+                mx0 = row_reduce_f(mx0, fmax2);
+                mx1 = row_reduce_f(mx1, fmax2);
+                // far-only when every row of the wave that wants this bit passed its near log-sum
+                const bool far_only = p < m && __ballot(want && !has_near) == 0ull;
+                float s0 = 0.0f, s1 = 0.0f;
+                if (far_only) {
+                    const int fb = mx1 < mx0 ? 1 : 0;  // the far subset: the smaller maximum
+                    const float mxf = fb ? mx1 : mx0;
+                    float sf = 0.0f;
+                    if (p < 4) {
+                        if (((r >> p) & 1) == fb) {
 #pragma unroll
-                for (int q = 0; q < NPL; ++q) sl += hw_exp2(t[q] - sh);
-                s0 = one ? 0.0f : sl;
-                s1 = one ? sl : 0.0f;
-            } else {
+                            for (int q = 0; q < NPL; ++q) sf += hw_exp2(t[q] - mxf);
+                        }
+                    } else {
 #pragma unroll
-                for (int q = 0; q < NPL; ++q) {
-                    if (p < m && ((q >> (p - 4)) & 1)) s1 += hw_exp2(t[q] - mx1);
-                    else s0 += hw_exp2(t[q] - mx0);
+                        for (int q = 0; q < NPL; ++q) {
+                            if (((q >> (p - 4)) & 1) == 0) {  // pair q with q | (1 << (p-4)); take the far one
+                                const float v = fb ? t[q | (1 << (p - 4))] : t[q];
+                                sf += hw_exp2(v - mxf);
+                            }
+                        }
+                    }
+                    sf = row_reduce_f(sf, fadd2);
+                    if (want && r == 0) {
+                        // L = log2 S1 - log2 S0 with the far subset's log-sum exact and the near one passed
+                        const float lf = mxf + hw_log2(sf);
+                        const float L = fb ? lf - near_lse : near_lse - lf;
+                        if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
+                        if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
+                    }
+                    continue;
                 }
-            }
-            s0 = row_reduce_f(s0, fadd2);
-            s1 = row_reduce_f(s1, fadd2);
-            if (want && r == 0) {
-                if (p < m) {
-                    const float L = (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
-                    if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
-                    if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
+                if (p < 4) {
+                    const bool one = ((r >> p) & 1) != 0;
+                    const float sh = one ? mx1 : mx0;
+                    float sl = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q) sl += hw_exp2(t[q] - sh);
+                    s0 = one ? 0.0f : sl;
+                    s1 = one ? sl : 0.0f;
                 } else {
-                    const float lse_all = mx0 + hw_log2(s0);
-                    const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
-                    mc += (double)((float)m - (lse_all - ttx));
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q) {
+                        if (p < m && ((q >> (p - 4)) & 1)) s1 += hw_exp2(t[q] - mx1);
+                        else s0 += hw_exp2(t[q] - mx0);
+                    }
+                }
+                s0 = row_reduce_f(s0, fadd2);
+                s1 = row_reduce_f(s1, fadd2);
+                if (want && r == 0) {
+                    if (p < m) {
+                        const float L = (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
+                        if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
+                        if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
+                    } else {
+                        const float lse_all = mx0 + hw_log2(s0);
+                        const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
+                        mc += (double)((float)m - (lse_all - ttx));
+                    }
                 }
             }
+            if (live && r == 0) {
+                add((int)e.tag, slot, 0, gc);
+                add((int)e.tag, slot, 1, mc);
+            }
         }
-        if (live && r == 0) {
-            add((int)e.tag, slot, 0, gc);
-            add((int)e.tag, slot, 1, mc);
-        }
+        __syncthreads();  // the chunk's entries are read before the next chunk overwrites them
     }
 }
 
