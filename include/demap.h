@@ -111,7 +111,8 @@ int dm_gmi_estimate(const dm_constellation* c, int n_snr, const double* sigma2,
  * holds until the process ends.  No hipMalloc, hipFree or allocating library call is made:
  * the constellation's MFMA operand tables are built by dm_constellation_create.
  *   Limits: n_snr <= 32 (DM_EINVAL beyond: the array holds 32 noise levels); any N < 2^31
- *   (a fix-up queue that fills up is recomputed in place by the demapping kernel).
+ *   (a symbol whose part of the fix-up queue is full is recomputed in place by the demapping
+ *   kernel).
  * Every call on a GPU shares that GPU's array, which keeps the last call's contents; each
  * call clears what must start at zero with a fill kernel.  Two calls whose launches overlapped
  * on one GPU would race on the array, so calls on one GPU are serialised: a host lock is held

@@ -18,7 +18,7 @@ struct dm_constellation {
     // scratch (grow-only), shared by calls on this constellation
     unsigned long long* d_acc = nullptr;  // kMaxSnrPerLaunch x kAccSlots x 2
     uint32_t* d_fix_pairs = nullptr;      // kMaxSnrPerLaunch + 1 (last word: bad-tx flag)
-    uint32_t* d_queue_count = nullptr;
+    uint32_t* d_queue_count = nullptr;    // kQueueCounterWords: the queue regions' counters
     dm::FixEntry* d_queue = nullptr;
     uint32_t queue_cap = 0;
     void* h_stage = nullptr;              // pinned: acc + fix_pairs
@@ -52,7 +52,7 @@ int ensure_frag(dm_constellation* c, int prec, bool pad8);
 int ensure_table8(dm_constellation* c);
 
 // Device scratch of one exact-path launch: fixed-point GMI / MI slots [kMaxSnrPerLaunch][kAccSlots][2],
-// fix-up pair counts [kMaxSnrPerLaunch] + bad-tx flag, fix-up queue and its counter.
+// fix-up pair counts [kMaxSnrPerLaunch] + bad-tx flag, fix-up queue and its region counters.
 struct ChunkScratch {
     unsigned long long* acc;
     uint32_t* fix_pairs;
@@ -61,7 +61,7 @@ struct ChunkScratch {
     uint32_t queue_cap;
 };
 // Exact path over up to 32 SNR points of one block on the given scratch, which the caller has
-// cleared (acc and fix_pairs when want_acc, queue_count always); allocates nothing (an MFMA
+// cleared (acc and fix_pairs when want_acc, the kQueueCounterWords of queue_count always); allocates nothing (an MFMA
 // precision needs its operand table built).  Caller holds c->mu.
 int run_chunk_on(dm_constellation* c, const ChunkScratch& scr, int n_snr, const double* sigma2,
                  const float* const* y, const uint16_t* tx, int64_t N, float* const* llr, bool want_acc, int prec,

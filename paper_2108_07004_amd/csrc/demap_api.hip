@@ -96,7 +96,7 @@ int ensure_scratch(dm_constellation* c, uint64_t want_queue) {
     if (!c->d_acc) {
         DM_HIP_TRY(hipMalloc(&c->d_acc, sizeof(unsigned long long) * dm::kMaxSnrPerLaunch * dm::kAccSlots * 2));
         DM_HIP_TRY(hipMalloc(&c->d_fix_pairs, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1)));
-        DM_HIP_TRY(hipMalloc(&c->d_queue_count, sizeof(uint32_t)));
+        DM_HIP_TRY(hipMalloc(&c->d_queue_count, sizeof(uint32_t) * dm::kQueueCounterWords));
         DM_HIP_TRY(hipHostMalloc(&c->h_stage, kStageBytes, hipHostMallocDefault));
     }
     const uint64_t cap = std::min<uint64_t>(std::max<uint64_t>(want_queue, 1024), 1u << 22);
@@ -306,7 +306,7 @@ int run_chunk(dm_constellation* c, int n_snr, const double* sigma2, const float*
         DM_HIP_TRY(hipMemsetAsync(c->d_acc, 0, sizeof(unsigned long long) * n_snr * dm::kAccSlots * 2, st));
         DM_HIP_TRY(hipMemsetAsync(c->d_fix_pairs, 0, sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1), st));
     }
-    DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t), st));
+    DM_HIP_TRY(hipMemsetAsync(c->d_queue_count, 0, sizeof(uint32_t) * dm::kQueueCounterWords, st));
     const ChunkScratch scr{c->d_acc, c->d_fix_pairs, c->d_queue_count, c->d_queue, c->queue_cap};
     return run_chunk_on(c, scr, n_snr, sigma2, y, tx, N, llr, want_acc, prec, st, sigma2_sym, true);
 }

@@ -2,7 +2,7 @@
 // device memory (code under stream capture, tight serving loops, harnesses that forbid it).
 //
 // The launch's scratch — fixed-point GMI / MI slots, fix-up pair counts and bad-tx flag, the
-// fix-up queue and its counter, and the per-point totals read back by the host — lives in one
+// fix-up queue and its region counters, and the per-point totals read back by the host — lives in one
 // file-scope device array, `scratch`, of kScratchBytes (about 16 MiB, held by every GPU the
 // library runs on until the process ends).  Host code never passes the array's name to a
 // kernel (on the host it is only a stand-in symbol): the device address is looked up once per
@@ -31,7 +31,7 @@ constexpr size_t kAccBytes = sizeof(unsigned long long) * dm::kMaxSnrPerLaunch *
 constexpr size_t kSumOff = kAccBytes;                                   // [n_snr][2] int64 totals
 constexpr size_t kFixOff = kSumOff + sizeof(long long) * dm::kMaxSnrPerLaunch * 2;
 constexpr size_t kCountOff = kFixOff + 256;                             // kMaxSnrPerLaunch + 1 words fit
-constexpr size_t kQueueOff = kCountOff + 256;
+constexpr size_t kQueueOff = kCountOff + sizeof(uint32_t) * dm::kQueueCounterWords;  // region counters
 constexpr size_t kClearBytes = kQueueOff;                               // zeroed by every call
 constexpr size_t kScratchBytes = kQueueOff + sizeof(dm::FixEntry) * kQueueEntries;
 static_assert(sizeof(uint32_t) * (dm::kMaxSnrPerLaunch + 1) <= 256, "fix-pair words overflow their slot");

@@ -111,7 +111,7 @@ struct dm_plan {
     std::vector<double> ns_per_pair;
     dm::BatchDesc* d_desc = nullptr;
     dm::WorkItem* d_items = nullptr;
-    uint32_t* d_words = nullptr;  // acc (2 words per int64) | fix_pairs[n] | bad_tx | queue_count
+    uint32_t* d_words = nullptr;  // acc (2 words per int64) | fix_pairs[n] | bad_tx | next | queue counters
     size_t n_words = 0;
     dm::FixEntry* d_queue = nullptr;
     uint32_t queue_cap = 0;
@@ -182,7 +182,10 @@ int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const
     DM_HIP_TRY(hipMemcpy(p->d_desc, desc.data(), desc.size() * sizeof(dm::BatchDesc), hipMemcpyHostToDevice));
     if (!items.empty())
         DM_HIP_TRY(hipMemcpy(p->d_items, items.data(), items.size() * sizeof(dm::WorkItem), hipMemcpyHostToDevice));
-    p->n_words = (size_t)p->n_inst * dm::kAccSlots * 2 * 2 + p->n_inst + 3;
+    // the queue's region counters start on a kQueueStride-word boundary after the other words
+    const size_t q_off = (((size_t)p->n_inst * dm::kAccSlots * 2 * 2 + p->n_inst + 2 + dm::kQueueStride - 1) /
+                          dm::kQueueStride) * dm::kQueueStride;
+    p->n_words = q_off + dm::kQueueCounterWords;
     DM_HIP_TRY(hipMalloc(&p->d_words, p->n_words * sizeof(uint32_t)));
     int64_t total_n = 0;
     for (const auto& in : p->inst) total_n += in.N;
@@ -195,11 +198,11 @@ int alloc_plan_buffers(dm_plan* p, const std::vector<dm::BatchDesc>& desc, const
     p->args.items = p->d_items;
     p->args.n_items = (int32_t)items.size();
     p->args.grab = p->grab;
-    p->args.next = tail + p->n_inst + 2;
+    p->args.next = tail + p->n_inst + 1;
     p->args.sinks.acc = acc;
     p->args.sinks.fix_pairs = tail;
     p->args.sinks.bad_tx = tail + p->n_inst;
-    p->args.sinks.queue_count = tail + p->n_inst + 1;
+    p->args.sinks.queue_count = p->d_words + q_off;
     p->args.sinks.queue = p->d_queue;
     p->args.sinks.queue_cap = p->queue_cap;
     return DM_OK;

@@ -10,6 +10,15 @@ constexpr int kAccSlots = 64;         // fixed-point accumulator slots per block
 constexpr double kFixScale = 268435456.0;  // 2^28: GMI/MI sums are accumulated as int64 * 2^-28
 constexpr uint32_t kMiFlag = 0x80000000u;  // fix-up mask bit: recompute the MI term
 
+// The fix-up queue is split into kQueueRegions equal regions, each with its own counter
+// (kQueueStride words apart): a wave appends to the region its global wave index hashes to.
+// Device-scope atomics on one address serialise at ~11 ns each on MI355X (measured), and at high
+// SNR nearly every 32-symbol batch queues symbols, so a single counter made the queue, not the
+// arithmetic, the bound of those launches; 64 counters spread the same atomics ~35x thinner.
+constexpr int kQueueRegions = 64;
+constexpr int kQueueStride = 64;                                   // words between two counters
+constexpr int kQueueCounterWords = kQueueRegions * kQueueStride;  // counter array, zeroed per launch
+
 // One symbol whose far-subset sums underflowed the shared exponent window.
 struct FixEntry {
     uint32_t n;     // symbol index within its block
@@ -51,8 +60,8 @@ struct Sinks {
     unsigned long long* acc;     // [tags][kAccSlots][2] int64 fixed-point GMI / MI sums, or null
     uint32_t* fix_pairs;         // [tags] count of (symbol, bit) pairs sent to the fix-up, or null
     uint32_t* bad_tx;            // set to 1 when a transmitted index is >= M (clamped, reported)
-    FixEntry* queue;
-    uint32_t* queue_count;
+    FixEntry* queue;             // queue_cap entries: kQueueRegions regions of queue_cap / kQueueRegions
+    uint32_t* queue_count;       // kQueueCounterWords: region r's counter at word r * kQueueStride
     uint32_t queue_cap;
 };
 
@@ -431,8 +440,8 @@ __device__ __forceinline__ float row_reduce_f(float v, Op op) {
 // once, the corrections are integer sums).
 constexpr int kFixSortChunk = 256;
 
-template <int DP, int NPL, typename ViewFn, typename AddFn>
-__device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count) {
+template <int DP, int NPL, typename ViewFn, typename AddFn, typename FetchFn, typename CountFn>
+__device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, CountFn count_pairs, uint32_t count) {
     constexpr int m = NPL == 8 ? 7 : 8;
     static_assert(NPL == 8 || NPL == 16, "row fix-up covers M = 128 and 256");
     __shared__ FixEntry s_sorted[kFixSortChunk];
@@ -455,7 +464,8 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count)
         FixEntry mine{};
         uint32_t key = 0u;
         if (have) {
-            mine = k.queue[c0 + tid];
+            mine = fetch(c0 + tid);
+            count_pairs(mine);
             key = mine.mask & 0xFFu;
             atomicAdd(&s_bin[key], 1u);
         }
@@ -586,7 +596,9 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, uint32_t count)
 // recomputed one per lane (fixup_one: cheaper than wave reductions for so few points), the
 // others one per wavefront (fixup_wave).  view(e) gives the block of a queue entry; tl is the
 // wave's LDS slice of cache_pts floats.  Corrections go to the fixed-point accumulators (slot = lane in the lane
-// pass, wave % kAccSlots in the wave pass).
+// pass, wave % kAccSlots in the wave pass).  The filled parts of the queue regions are read as
+// one list (entry i lies in the region whose prefix range holds i); every entry's flagged
+// pairs are added to fix_pairs[tag] here.
 constexpr int kFixLaneMaxM = 64;
 
 template <int DP, typename ViewFn>
@@ -596,8 +608,39 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
     // flushed once per workgroup: per-entry global atomics were the fix-up's bottleneck.
     constexpr int kFixLdsTags = 64;
     __shared__ unsigned long long s_acc[kFixLdsTags * 2];
+    __shared__ uint32_t s_pairs[kFixLdsTags];
+    __shared__ uint32_t s_qpre[kQueueRegions + 1];  // exclusive prefix of the regions' fill
+    static_assert(kQueueRegions == 64, "one wave scans the region counts");
     for (int i = threadIdx.x; i < kFixLdsTags * 2; i += blockDim.x) s_acc[i] = 0ull;
+    for (int i = threadIdx.x; i < kFixLdsTags; i += blockDim.x) s_pairs[i] = 0u;
+    const uint32_t seg = k.queue_cap / kQueueRegions;
+    if (threadIdx.x < 64) {  // wave 0, fully active
+        const int r = threadIdx.x;
+        uint32_t x = min(k.queue_count[r * kQueueStride], seg);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (r >= off) x += y;
+        }
+        s_qpre[r + 1] = x;
+        if (r == 0) s_qpre[0] = 0u;
+    }
     __syncthreads();
+    // entry i < count: the largest region r with s_qpre[r] <= i holds it at offset i - s_qpre[r]
+    auto fetch = [&](uint32_t i) -> FixEntry {
+        uint32_t r = 0;
+#pragma unroll
+        for (uint32_t step = kQueueRegions / 2; step >= 1; step >>= 1)
+            if (s_qpre[r + step] <= i) r += step;
+        return k.queue[(size_t)r * seg + (i - s_qpre[r])];
+    };
+    auto count_pairs = [&](const FixEntry& e) {
+        if (!k.fix_pairs) return;
+        const uint32_t c = (uint32_t)__popc(e.mask & 0xFFFFu);
+        if (c == 0u) return;
+        if (e.tag < (uint32_t)kFixLdsTags) atomicAdd(&s_pairs[e.tag], c);
+        else atomicAdd(k.fix_pairs + e.tag, c);
+    };
     auto add = [&](int tag, int slot, int which, double v) {
         if (!k.acc) return;
         if (tag < kFixLdsTags) {
@@ -607,19 +650,20 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
             acc_add(k.acc, tag, slot, which, v);
         }
     };
-    uint32_t count = min(*k.queue_count, k.queue_cap);
+    uint32_t count = s_qpre[kQueueRegions];
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     if (uniform_M == 128 || uniform_M == 256) {  // every entry has that M: four symbols per wave
-        if (uniform_M == 128) fix_rows<DP, 8>(k, view, add, count);
-        else fix_rows<DP, 16>(k, view, add, count);
+        if (uniform_M == 128) fix_rows<DP, 8>(k, view, add, fetch, count_pairs, count);
+        else fix_rows<DP, 16>(k, view, add, fetch, count_pairs, count);
         count = 0;  // nothing left for the lane and wave passes
     }
     for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
         const uint32_t i = base + lane;
         if (i < count) {
-            const FixEntry e = k.queue[i];
+            const FixEntry e = fetch(i);
+            count_pairs(e);
             const BlockView b = view(e);
             if (b.M <= kFixLaneMaxM) {
                 double gc = 0.0, mc = 0.0;
@@ -631,7 +675,7 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
     }
     const int slot = (int)(wave % kAccSlots);
     for (uint32_t i = wave; i < count; i += nwaves) {
-        const FixEntry e = k.queue[i];
+        const FixEntry e = fetch(i);
         const BlockView b = view(e);
         if (b.M > kFixLaneMaxM) {
             double gc = 0.0, mc = 0.0;
@@ -648,18 +692,34 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
         for (int i = threadIdx.x; i < kFixLdsTags * 2; i += blockDim.x)
             if (s_acc[i] != 0ull) atomicAdd(k.acc + ((size_t)(i >> 1) * kAccSlots + bslot) * 2 + (i & 1), s_acc[i]);
     }
+    if (k.fix_pairs)
+        for (int i = threadIdx.x; i < kFixLdsTags; i += blockDim.x)
+            if (s_pairs[i] != 0u) atomicAdd(k.fix_pairs + i, s_pairs[i]);
 }
 
-// Queue a symbol for the fix-up (near: FixEntry.near of the symbol); when the queue is full the
-// calling lane recomputes it in place (slow but exact) and the corrections come back through
-// gc / mc.
+// Queue region of the calling wave (wave-uniform, so the compiler folds the lanes' counter
+// increments into one atomic per wave).
+__device__ __forceinline__ uint32_t queue_region() {
+    const uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(w % kQueueRegions));
+}
+
+// Queue a symbol for the fix-up (near: FixEntry.near of the symbol) in the wave's region; when
+// that region is full the calling lane recomputes the symbol in place (slow but exact), counts
+// its pairs, and the corrections come back through gc / mc.  Queued pairs are counted by the
+// fix-up when it drains them.
 template <int DP>
 __device__ __forceinline__ void queue_or_fix(const BlockView& b, const Sinks& k, uint32_t n, uint32_t mask,
                                              uint32_t near, double& gc, double& mc) {
-    if (k.fix_pairs) atomicAdd(k.fix_pairs + b.tag, (uint32_t)__popc(mask & 0xFFFFu));
-    const uint32_t slot = atomicAdd(k.queue_count, 1u);
-    if (slot < k.queue_cap) k.queue[slot] = FixEntry{n, (uint32_t)b.tag, mask, near};
-    else fixup_one<DP>(b, k, n, mask, gc, mc);
+    const uint32_t seg = k.queue_cap / kQueueRegions;
+    const uint32_t r = queue_region();
+    const uint32_t slot = atomicAdd(k.queue_count + r * kQueueStride, 1u);
+    if (slot < seg) {
+        k.queue[(size_t)r * seg + slot] = FixEntry{n, (uint32_t)b.tag, mask, near};
+    } else {
+        if (k.fix_pairs) atomicAdd(k.fix_pairs + b.tag, (uint32_t)__popc(mask & 0xFFFFu));
+        fixup_one<DP>(b, k, n, mask, gc, mc);
+    }
 }
 
 }  // namespace dm
