@@ -9,6 +9,13 @@ constexpr int kMaxSnrPerLaunch = 32;  // SNR points per launch (kernel-argument 
 constexpr int kAccSlots = 64;         // fixed-point accumulator slots per block (spreads atomics)
 constexpr double kFixScale = 268435456.0;  // 2^28: GMI/MI sums are accumulated as int64 * 2^-28
 constexpr uint32_t kMiFlag = 0x80000000u;  // fix-up mask bit: recompute the MI term
+constexpr int kFarShift = 16;  // fix-up mask bit kFarShift + p: bit p's far subset is its bit-1 side
+constexpr int kFarBits = 15;   // label bits p < kFarBits carry that side (bits 16..30 of the mask)
+
+// Fix-up mask of a flagged label bit p with subset sums s0 / s1 (the far side: the smaller).
+__device__ __forceinline__ uint32_t flag_bits(int p, float s0, float s1) {
+    return (1u << p) | ((p < kFarBits && s1 < s0) ? 1u << (kFarShift + p) : 0u);
+}
 
 // The fix-up queue is split into kQueueRegions equal regions, each with its own counter
 // (kQueueStride words apart): a wave appends to the region its global wave index hashes to.
@@ -23,7 +30,8 @@ constexpr int kQueueCounterWords = kQueueRegions * kQueueStride;  // counter arr
 struct FixEntry {
     uint32_t n;     // symbol index within its block
     uint32_t tag;   // block (SNR point or instance) the symbol belongs to
-    uint32_t mask;  // bit p set: recompute label bit p; kMiFlag: recompute the MI term
+    uint32_t mask;  // bit p set: recompute label bit p (p < 16); kMiFlag: recompute the MI term;
+                    // bit kFarShift + p: bit p's far (underflowed) subset is the bit-1 side
     uint32_t near;  // bits of log2 of the symbol's total sum (t units) when that total is at least
                     // 2^(m-78) and finite (kNearNone otherwise): then a flagged bit's near subset
                     // holds all of it to FP32 precision, and only its far subset needs recomputing
@@ -423,14 +431,14 @@ __device__ __forceinline__ float row_reduce_f(float v, Op op) {
 // Row fix-up for a constellation of M = 16 * NPL points (M = 128 or 256, the same for every
 // queued symbol): each 16-lane row of a wavefront takes one queued symbol, so a wavefront
 // recomputes four at once.  Lane r of a row keeps the exponents t = K - c ||y - x_j||^2 of labels
-// j = r + 16 q in registers; label bits 0-3 of j are bits of r, bits 4 and up bits of q.  The bit
-// loop is unrolled, so every subset split is known at compile time: for p < 4 a lane's 16 values
-// all lie in one subset, for p >= 4 the registers split in halves.  Each flagged bit first takes
-// both subset maxima (row reductions).  When the queue entry carries the near-subset log-sum
-// (FixEntry.near), only the far subset -- the one with the smaller maximum -- is summed under
-// its maximum and L = (far log-sum) - (near log-sum) with the sign of the far bit; otherwise
-// both subsets are summed under their own maxima (the two-pass log-sum-exp of
-// wave_exact_llr2).  Lane 0 of the row writes the LLR and accumulates the GMI / MI
+// j = r + 16 q in registers (less the flag bound m - 102); label bits 0-3 of j are bits of r,
+// bits 4 and up bits of q.  The bit loop is unrolled, so every subset split is known at compile
+// time: for p < 4 a lane's 16 values all lie in one subset, for p >= 4 the registers split in
+// halves.  When the queue entry carries the near-subset log-sum (FixEntry.near) and the far side
+// of the bit (mask bit kFarShift + p), only the far subset is summed, under the flag bound its
+// terms all lie below (no maxima), and L = (far log-sum) - (near log-sum) with the sign of the
+// far bit; otherwise both subsets are summed under their own maxima (the two-pass log-sum-exp
+// of wave_exact_llr2).  Lane 0 of the row writes the LLR and accumulates the GMI / MI
 // corrections, which add(tag, slot, which, value) receives.
 //
 // A wave's four rows run the bit loop for the union of their flagged bits, so the queue is taken
@@ -496,88 +504,103 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
             float y[DP];
             load_symbol<DP>(y, b.y + (size_t)e.n * b.D, b.D, true);
             const int txl = b.tx ? tx_label(b, k, e.n) : 0;
-            float t[NPL];
+            // Exponents relative to the flag bound sh = m - 102, below which every term of a far
+            // subset lies: u_j = t_j - sh = (K - sh) - c ||y - x_j||^2.
+            constexpr float sh = (float)(m - 102);
+            float u[NPL];
 #pragma unroll
-            for (int q = 0; q < NPL; ++q) t[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K);
+            for (int q = 0; q < NPL; ++q)
+                u[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K - sh);
             double gc = 0.0, mc = 0.0;
             // p = 0 .. m-1: label bits; p = m: the MI term (every point in subset 0).
 #pragma unroll
             for (int p = 0; p <= m; ++p) {
                 const bool want = p < m ? ((mask >> p) & 1u) != 0u : ((mask & kMiFlag) != 0u && b.tx != nullptr);
                 if (__ballot(want) == 0ull) continue;
-                // subset maxima
+                // Far-only for a row that passed its near log-sum and the far side of the bit: the
+                // far subset is summed under the fixed shift sh, all its terms being below 2^0.  A
+                // sum of at least 2^-95 holds its largest term above 2^-102, so the terms flushed
+                // below 2^-126 are under 2^-24 of the sum.  Every other row takes the two-pass path
+                // below; each row's choice depends on its own symbol only, so the results do not
+                // depend on which queue entries share a wavefront.
+                bool far_ok = false;
+                if (p < m && p < kFarBits && __ballot(want && has_near) != 0ull) {
+                    const int fb = (int)((mask >> (kFarShift + p)) & 1u);
+                    // all-ones when the far side is bit 1; opaque, so that the pick below stays a
+                    // bit select (a select of the two registers by fb could be turned into a
+                    // run-time index into u, which would put u in scratch memory)
+                    uint32_t pick1 = 0u - (uint32_t)fb;
+                    asm volatile("" : "+v"(pick1));
+                    float sf = 0.0f;
+                    if (p < 4) {
+                        if (((r >> p) & 1) == fb) {
+#pragma unroll
+                            for (int q = 0; q < NPL; ++q) sf += hw_exp2(u[q]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NPL; ++q) {
+                            if (((q >> (p - 4)) & 1) == 0) {  // pair q with q | (1 << (p-4)); take the far one
+                                const uint32_t v0 = __builtin_bit_cast(uint32_t, u[q]);
+                                const uint32_t v1 = __builtin_bit_cast(uint32_t, u[q | (1 << (p - 4))]);
+                                sf += hw_exp2(__builtin_bit_cast(float, (v1 & pick1) | (v0 & ~pick1)));
+                            }
+                        }
+                    }
+                    sf = row_reduce_f(sf, fadd2);
+                    far_ok = has_near && sf >= 0x1p-95f;
+                    if (want && far_ok && r == 0) {
+                        // L = log2 S1 - log2 S0: the far log-sum exact, the near one passed
+                        const float lf = sh + hw_log2(sf);
+                        const float L = fb ? lf - near_lse : near_lse - lf;
+                        if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
+                        if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
+                    }
+                }
+                if (__ballot(want && !far_ok) == 0ull) continue;
+                // Two-pass log-sum-exp of both subsets: maxima, then sums under them.
                 float mx0 = -INFINITY, mx1 = -INFINITY;
                 if (p < 4) {
-                    float mxl = t[0];
+                    float mxl = u[0];
 #pragma unroll
-                    for (int q = 1; q < NPL; ++q) mxl = fmaxf(mxl, t[q]);
+                    for (int q = 1; q < NPL; ++q) mxl = fmaxf(mxl, u[q]);
                     const bool one = ((r >> p) & 1) != 0;
                     mx0 = one ? -INFINITY : mxl;
                     mx1 = one ? mxl : -INFINITY;
                 } else {
 #pragma unroll
                     for (int q = 0; q < NPL; ++q) {
-                        if (p < m && ((q >> (p - 4)) & 1)) mx1 = fmaxf(mx1, t[q]);
-                        else mx0 = fmaxf(mx0, t[q]);
+                        if (p < m && ((q >> (p - 4)) & 1)) mx1 = fmaxf(mx1, u[q]);
+                        else mx0 = fmaxf(mx0, u[q]);
                     }
                 }
                 mx0 = row_reduce_f(mx0, fmax2);
                 mx1 = row_reduce_f(mx1, fmax2);
-                // far-only when every row of the wave that wants this bit passed its near log-sum
-                const bool far_only = p < m && __ballot(want && !has_near) == 0ull;
                 float s0 = 0.0f, s1 = 0.0f;
-                if (far_only) {
-                    const int fb = mx1 < mx0 ? 1 : 0;  // the far subset: the smaller maximum
-                    const float mxf = fb ? mx1 : mx0;
-                    float sf = 0.0f;
-                    if (p < 4) {
-                        if (((r >> p) & 1) == fb) {
-#pragma unroll
-                            for (int q = 0; q < NPL; ++q) sf += hw_exp2(t[q] - mxf);
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < NPL; ++q) {
-                            if (((q >> (p - 4)) & 1) == 0) {  // pair q with q | (1 << (p-4)); take the far one
-                                const float v = fb ? t[q | (1 << (p - 4))] : t[q];
-                                sf += hw_exp2(v - mxf);
-                            }
-                        }
-                    }
-                    sf = row_reduce_f(sf, fadd2);
-                    if (want && r == 0) {
-                        // L = log2 S1 - log2 S0 with the far subset's log-sum exact and the near one passed
-                        const float lf = mxf + hw_log2(sf);
-                        const float L = fb ? lf - near_lse : near_lse - lf;
-                        if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
-                        if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
-                    }
-                    continue;
-                }
                 if (p < 4) {
                     const bool one = ((r >> p) & 1) != 0;
-                    const float sh = one ? mx1 : mx0;
+                    const float sl_shift = one ? mx1 : mx0;
                     float sl = 0.0f;
 #pragma unroll
-                    for (int q = 0; q < NPL; ++q) sl += hw_exp2(t[q] - sh);
+                    for (int q = 0; q < NPL; ++q) sl += hw_exp2(u[q] - sl_shift);
                     s0 = one ? 0.0f : sl;
                     s1 = one ? sl : 0.0f;
                 } else {
 #pragma unroll
                     for (int q = 0; q < NPL; ++q) {
-                        if (p < m && ((q >> (p - 4)) & 1)) s1 += hw_exp2(t[q] - mx1);
-                        else s0 += hw_exp2(t[q] - mx0);
+                        if (p < m && ((q >> (p - 4)) & 1)) s1 += hw_exp2(u[q] - mx1);
+                        else s0 += hw_exp2(u[q] - mx0);
                     }
                 }
                 s0 = row_reduce_f(s0, fadd2);
                 s1 = row_reduce_f(s1, fadd2);
-                if (want && r == 0) {
+                if (want && !far_ok && r == 0) {
                     if (p < m) {
                         const float L = (mx1 - mx0) + (hw_log2(s1) - hw_log2(s0));
                         if (b.llr) b.llr[(size_t)e.n * m + (m - 1 - p)] = L * 0.69314718055994531f;
                         if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
                     } else {
-                        const float lse_all = mx0 + hw_log2(s0);
+                        const float lse_all = (mx0 + hw_log2(s0)) + sh;
                         const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
                         mc += (double)((float)m - (lse_all - ttx));
                     }

@@ -32,8 +32,29 @@ __global__ __launch_bounds__(kHardThreads) void hard_demap_kernel(const HardArgs
         __syncthreads();
     }
     const int64_t total = a.tiles_per_blk * a.n_blk;
+    // Error counts accumulate per lane and go out once per received block and wave: one counter
+    // address per block, and device-scope atomics on one address serialise (~11 ns each).
+    uint32_t se = 0, be = 0;
+    int cur = -1;
+    auto flush = [&]() {
+        if (cur < 0 || !a.counts) return;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            se += __shfl_xor(se, off, 64);
+            be += __shfl_xor(be, off, 64);
+        }
+        if (lane == 0) {
+            if (se) atomicAdd(a.counts + 2 * cur, (unsigned long long)se);
+            if (be) atomicAdd(a.counts + 2 * cur + 1, (unsigned long long)be);
+        }
+        se = be = 0;
+    };
     for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int s = (int)(tile / a.tiles_per_blk);
+        if (s != cur) {  // block-uniform
+            flush();
+            cur = s;
+        }
         const int64_t n = (tile % a.tiles_per_blk) * kHardThreads + tid;
         const bool active = n < a.N;
         float y[DP];
@@ -63,29 +84,18 @@ __global__ __launch_bounds__(kHardThreads) void hard_demap_kernel(const HardArgs
             }
         }
         if (active && a.labels_out[s]) a.labels_out[s][n] = (uint16_t)arg;
-        if (a.counts) {
-            uint32_t se = 0, be = 0;
-            if (active) {
-                uint32_t row = a.tx[n];
-                if (row >= (uint32_t)M) {
-                    atomicOr(a.bad_tx, 1u);
-                    row = 0;
-                }
-                const uint32_t txl = a.row2label[row];
-                se = (uint32_t)arg != txl;
-                be = __builtin_popcount((uint32_t)arg ^ txl);
+        if (a.counts && active) {
+            uint32_t row = a.tx[n];
+            if (row >= (uint32_t)M) {
+                atomicOr(a.bad_tx, 1u);
+                row = 0;
             }
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                se += __shfl_xor(se, off, 64);
-                be += __shfl_xor(be, off, 64);
-            }
-            if (lane == 0) {
-                if (se) atomicAdd(a.counts + 2 * s, (unsigned long long)se);
-                if (be) atomicAdd(a.counts + 2 * s + 1, (unsigned long long)be);
-            }
+            const uint32_t txl = a.row2label[row];
+            se += (uint32_t)arg != txl;
+            be += __builtin_popcount((uint32_t)arg ^ txl);
         }
     }
+    flush();
 }
 
 template <int DP>

@@ -378,7 +378,7 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
                         (bit ? s1 > s0 : s0 > s1))
                         g += 1.0f;
                     else
-                        mask |= 1u << p;
+                        mask |= flag_bits(p, s0, s1);
                 }
             }
         }

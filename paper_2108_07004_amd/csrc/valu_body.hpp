@@ -100,7 +100,7 @@ __device__ __forceinline__ void valu_epilogue(const BlockView& b, const Sinks& k
         } else if (!b.want_llr && fmaxf(s0, s1) >= b.near_thresh && (bit ? s1 > s0 : s0 > s1)) {
             g += 1.0f;  // |L| >= 60 with the transmitted bit on the near side: term is 1 in FP64
         } else {
-            mask |= 1u << p;
+            mask |= flag_bits(p, s0, s1);
         }
     }
     if (b.tx) {
