@@ -1,8 +1,10 @@
 // Exact soft demapper for constellations of 32 to 256 points (one to eight 32-point tiles) with
 // the distance cross term on MFMA (gfx950): the multi-SNR launch over one constellation with the
 // tile count fixed at compile time (tile loop and subset sums in mfma_small.hpp, epilogue in
-// mfma_body.hpp).  The whole operand table (at most 8 tiles x 2 MFMAs x 1 KiB) is staged in LDS
-// once per block.
+// mfma_body.hpp).  The whole operand table (at most 8 tiles x 2 MFMAs x 1 KiB), the per-label
+// operand rows of the MI term (at most 16 KiB) and the row-to-label map are staged in LDS once
+// per block, so that the transmitted label and its operand row, read once per batch, cost LDS
+// rather than global-memory latency.
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "mfma_body.hpp"
@@ -20,7 +22,9 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
                                                                     const uint16_t* __restrict__ pv) {
     constexpr int S = Slots<D, SPLIT>::S;
     constexpr int MB = SmallBits<NT>::MB;  // label bits of the constellation
-    __shared__ uint4 lds_frag[NT * S * 64];  // [tile][s][lane] x 16 bytes
+    __shared__ uint4 lds_frag[NT * S * 64];     // [tile][s][lane] x 16 bytes
+    __shared__ uint4 lds_pv[NT * 32 * 2 * S];   // [label][16 S halves]
+    __shared__ uint16_t lds_r2l[NT * 32];       // row -> label
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int h = lane >> 5;
@@ -28,6 +32,8 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
     const int wave_slot = (blockIdx.x * kWaves + wave) % kAccSlots;
     const Sinks& k = a.sinks;
     for (int i = tid; i < NT * S * 64; i += kThreads) lds_frag[i] = frag[i];
+    for (int i = tid; i < NT * 32 * 2 * S; i += kThreads) lds_pv[i] = reinterpret_cast<const uint4*>(pv)[i];
+    for (int i = tid; i < NT * 32; i += kThreads) lds_r2l[i] = a.row2label[i];
     __syncthreads();
 
     const int64_t sym_per_blk = (int64_t)kWaves * 32;
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
                 if (k.bad_tx) atomicOr(k.bad_tx, 1u);
                 row = 0;
             }
-            txl = (int)b.row2label[row];
+            txl = (int)lds_r2l[row];
         }
         bool bad = false;
         const Frags<T, S> bfr = build_symbol_frags<T, D, SPLIT>(y, b.c, b.K, h, bad);
@@ -92,7 +98,8 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
         float S0[MB], S1[MB], tot;
         mfma_small_sums<T, D, SPLIT, NT>(lds_frag, lane, bfr, S0, S1, tot);
         float g, mi;
-        mfma_finish<T, D, SPLIT, MB>(b, k, pv, bfr, S0, S1, tot, n, active, bad, txl, lane, g, mi);
+        mfma_finish<T, D, SPLIT, MB>(b, k, reinterpret_cast<const uint16_t*>(lds_pv), bfr, S0, S1, tot, n, active, bad,
+                                     txl, lane, g, mi);
         if (k.acc && active) {
             gsum += (double)g;
             msum += (double)mi;

@@ -377,8 +377,10 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
                     if (!bad_sym && !b.want_llr && fmaxf(s0, s1) >= b.near_thresh && fmaxf(s0, s1) < 3.0e38f &&
                         (bit ? s1 > s0 : s0 > s1))
                         g += 1.0f;
+                    else if constexpr (MB <= 8)
+                        mask |= flag_bits(p, s0, s1);  // the row fix-up of M <= 256 uses the far side
                     else
-                        mask |= flag_bits(p, s0, s1);
+                        mask |= 1u << p;
                 }
             }
         }
@@ -396,10 +398,33 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
             dg = Mma<T>::run(__builtin_bit_cast(V, *(const uint4*)(pr + 16 * s2)), bfr.v[s2], dg);
         const int j = lane & 31;
         int rd = 4 * (j >> 3) + (j & 3);
-        asm volatile("" : "+v"(rd));  // keeps the 15 lane masks below from being hoisted out of the loop
-        float v = dg[0];
+        asm volatile("" : "+v"(rd));  // keeps the lane masks below from being hoisted out of the loop
+        float v;
+        if constexpr (MB <= 8) {
+            // dg[rd] by a four-level tree of bit selects (all-ones masks from the bits of rd): no
+            // serial compare chain, and no run-time register index for the compiler to form.
+            // The constellations of up to 256 points have the registers for it; the larger ones,
+            // at the 128-register cap, keep the compare chain below.
+            // (each element is copied to a scalar before the bit cast: this compiler casts
+            // element 0 for a bit cast applied to an element of a vector-typed value)
+            uint32_t w[16];
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v = (rd == r) ? dg[r] : v;
+            for (int r = 0; r < 16; ++r) {
+                const float f = dg[r];
+                w[r] = __builtin_bit_cast(uint32_t, f);
+            }
+#pragma unroll
+            for (int lvl = 0; lvl < 4; ++lvl) {
+                const uint32_t pick = 0u - (((uint32_t)rd >> lvl) & 1u);  // 0 or all ones
+#pragma unroll
+                for (int i = 0; i < (8 >> lvl); ++i) w[i] = (w[2 * i + 1] & pick) | (w[2 * i] & ~pick);
+            }
+            v = __builtin_bit_cast(float, w[0]);
+        } else {
+            v = dg[0];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) v = (rd == r) ? dg[r] : v;
+        }
         // The lane half (j >> 2) & 1 holds the diagonal element; after the swap it is r1 if
         // that half is the upper one, else r0, in both halves.
         uint32_t v0, v1;
