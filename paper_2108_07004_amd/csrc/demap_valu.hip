@@ -87,7 +87,7 @@ template <int DP>
 __global__ __launch_bounds__(256) void fixup_kernel(const LaunchArgs a, int cache_pts) {
     extern __shared__ float s_t[];  // per-wave exponent caches, 4 x cache_pts floats
     drain_fix_queue<DP>(a.sinks, [&](const FixEntry& e) { return view_sym(a, (int)e.tag, e.n, true); },
-                        s_t + (threadIdx.x >> 6) * cache_pts, cache_pts, a.M);
+                        s_t + (threadIdx.x >> 6) * cache_pts, cache_pts, a.M, a.table);
 }
 
 template <int DP>

@@ -449,9 +449,20 @@ __device__ __forceinline__ float row_reduce_f(float v, Op op) {
 constexpr int kFixSortChunk = 256;
 
 template <int DP, int NPL, typename ViewFn, typename AddFn, typename FetchFn, typename CountFn>
-__device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, CountFn count_pairs, uint32_t count) {
+__device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, CountFn count_pairs, uint32_t count,
+                         const float* table) {
     constexpr int m = NPL == 8 ? 7 : 8;
     static_assert(NPL == 8 || NPL == 16, "row fix-up covers M = 128 and 256");
+    // The point table (every queued symbol's, label order) in LDS: each row reads all of it, and
+    // from global memory those NPL loads per lane and symbol were the kernel's latency bound.
+    constexpr int kTab = DP <= 8 ? 16 * NPL * DP : 1;
+    __shared__ __align__(16) float s_tab[kTab];
+    const float* tab = table;
+    if constexpr (DP <= 8) {
+        for (int i = threadIdx.x; i < kTab; i += blockDim.x) s_tab[i] = table[i];
+        __syncthreads();
+        tab = s_tab;
+    }
     __shared__ FixEntry s_sorted[kFixSortChunk];
     __shared__ uint32_t s_bin[256];
     __shared__ uint32_t s_wsum[kFixSortChunk / 64];
@@ -510,7 +521,7 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
             float u[NPL];
 #pragma unroll
             for (int q = 0; q < NPL; ++q)
-                u[q] = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)(r + 16 * q) * DP), b.K - sh);
+                u[q] = fmaf(-b.c, sqdist<DP>(y, tab + (r + 16 * q) * DP), b.K - sh);
             double gc = 0.0, mc = 0.0;
             // p = 0 .. m-1: label bits; p = m: the MI term (every point in subset 0).
 #pragma unroll
@@ -601,7 +612,7 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
                         if (b.tx) gc += (double)gmi_bit_term(L, (txl >> p) & 1);
                     } else {
                         const float lse_all = (mx0 + hw_log2(s0)) + sh;
-                        const float ttx = fmaf(-b.c, sqdist<DP>(y, b.table + (size_t)txl * DP), b.K);
+                        const float ttx = fmaf(-b.c, sqdist<DP>(y, tab + txl * DP), b.K);
                         mc += (double)((float)m - (lse_all - ttx));
                     }
                 }
@@ -625,7 +636,8 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
 constexpr int kFixLaneMaxM = 64;
 
 template <int DP, typename ViewFn>
-__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cache_pts, int uniform_M = 0) {
+__device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cache_pts, int uniform_M = 0,
+                                const float* uniform_table = nullptr) {
     // Corrections of blocks (tags) below kFixLdsTags are summed per workgroup in LDS, as the same
     // fixed-point integers acc_add uses (so the totals are unchanged and order-independent), and
     // flushed once per workgroup: per-entry global atomics were the fix-up's bottleneck.
@@ -677,9 +689,9 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
     const int lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    if (uniform_M == 128 || uniform_M == 256) {  // every entry has that M: four symbols per wave
-        if (uniform_M == 128) fix_rows<DP, 8>(k, view, add, fetch, count_pairs, count);
-        else fix_rows<DP, 16>(k, view, add, fetch, count_pairs, count);
+    if ((uniform_M == 128 || uniform_M == 256) && uniform_table) {  // one constellation: four symbols per wave
+        if (uniform_M == 128) fix_rows<DP, 8>(k, view, add, fetch, count_pairs, count, uniform_table);
+        else fix_rows<DP, 16>(k, view, add, fetch, count_pairs, count, uniform_table);
         count = 0;  // nothing left for the lane and wave passes
     }
     for (uint32_t base = wave * 64; base < count; base += nwaves * 64) {
