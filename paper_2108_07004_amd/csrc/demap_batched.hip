@@ -13,6 +13,7 @@
 // tables use a row stride of 8 (D <= 8 zero-padded): the padded coordinates contribute exact
 // zeros, and the MFMA operand vectors of every instance have the same K layout.
 #include "device_common.hpp"
+#include "fixup_drain.hpp"
 #include "kernels.hpp"
 #include "mfma_body.hpp"
 #include "mfma_small.hpp"

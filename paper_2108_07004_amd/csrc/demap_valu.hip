@@ -4,6 +4,7 @@
 // staged in LDS and read with wave-uniform addresses (broadcast); the per-symbol arithmetic is
 // in valu_body.hpp.  A persistent grid walks (SNR point, 512-symbol tile) work items.
 #include "device_common.hpp"
+#include "fixup_drain.hpp"
 #include "kernels.hpp"
 #include "valu_body.hpp"
 
