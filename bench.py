@@ -483,6 +483,9 @@ def main():
     rates = dm.probe_valu_rates()
     log(f"probe: exp2 {rates['exp2_per_s'] / 1e12:.2f} T/s, fma {rates['fma_per_s'] / 1e12:.2f} T/s, "
         f"exp2+2add {rates['exp2_add2_per_s'] / 1e12:.2f} T/s")
+    atom = dm.probe_atomic_rates()
+    log(f"probe: device atomics {1e9 / atom['one_address_per_s']:.2f} ns each on one address, "
+        f"{1e9 / atom['spread_per_s']:.3f} ns over {atom['spread_addresses']} addresses")
 
     gmi = mi = None
     for _ in range(args.warmup):
@@ -537,7 +540,10 @@ def main():
         "kernel": {"demap_ms": main_ms / max(launches, 1), "fixup_ms": fix_ms / max(launches, 1),
                    "fixup_pairs": int(fix_total),
                    "probe_exp2_Tps": rates["exp2_per_s"] / 1e12, "probe_fma_Tps": rates["fma_per_s"] / 1e12,
-                   "probe_exp2_add2_Tps": rates["exp2_add2_per_s"] / 1e12},
+                   "probe_exp2_add2_Tps": rates["exp2_add2_per_s"] / 1e12,
+                   # ns per device-scope atomic, all on one address / over the fix-up queue's 64 counters
+                   "probe_atomic_ns_one_address": 1e9 / atom["one_address_per_s"],
+                   "probe_atomic_ns_64_addresses": 1e9 / atom["spread_per_s"]},
         "gmi": [round(float(v), 6) for v in gmi],
         "ngmi": [round(float(v) / w.const.m, 6) for v in gmi],
     }

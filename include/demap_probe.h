@@ -26,6 +26,17 @@ extern "C" {
 int dm_probe_valu_rates(double* rates, void* stream);
 
 /*
+ * Measure device-scope atomic throughput on the current device, synchronously on `stream`:
+ * one lane of each of (compute units x 16) wavefronts issues 32 atomicAdds.
+ *   rates[0]  atomics per second when all of them target one 32-bit word
+ *   rates[1]  atomics per second when wavefront w targets word (w % 64) of 64 words spaced
+ *             256 bytes apart (the layout of the fix-up queue's region counters)
+ *   rates[2]  number of words used for rates[1] (64)
+ * Returns 0, -1 (null argument), -3 (HIP error) or -4 (allocation failed).
+ */
+int dm_probe_atomic_rates(double* rates, void* stream);
+
+/*
  * Kernel timing with HIP events recorded on the launch stream around the demapping
  * kernel and around the fix-up kernel of every later dm_demap_llr / dm_gmi_estimate
  * call on this thread.  dm_profile_enable(1) starts (and clears), 0 stops.

@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = ["Constellation", "DemapError", "MLP", "PREC", "Plan", "demap_batched", "demap_learned", "demap_llr",
            "demap_llr_var", "gmi_estimate", "gs_optimize", "hard_decision", "q_factor_db", "Streamer", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
-           "probe_valu_rates", "profile_enable", "profile_read"]
+           "probe_valu_rates", "probe_atomic_rates", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}
@@ -60,6 +60,8 @@ def load_library():
     lib.dm_last_fixup_count.restype = I64
     lib.dm_probe_valu_rates.argtypes = [P, P]
     lib.dm_probe_valu_rates.restype = I
+    lib.dm_probe_atomic_rates.argtypes = [P, P]
+    lib.dm_probe_atomic_rates.restype = I
     lib.dm_profile_enable.argtypes = [I]
     lib.dm_profile_enable.restype = I
     lib.dm_profile_read.argtypes = [P, P, P, I]
@@ -252,6 +254,15 @@ def probe_valu_rates(stream=None) -> dict:
     if rc != 0:
         raise DemapError(rc, "dm_probe_valu_rates failed")
     return {"exp2_per_s": r[0], "fma_per_s": r[1], "exp2_add2_per_s": r[2], "cus": int(r[3])}
+
+
+def probe_atomic_rates(stream=None) -> dict:
+    """Measured device-scope atomic rates on one address and over 64 (dm_probe_atomic_rates)."""
+    r = np.zeros(3, dtype=np.float64)
+    rc = load_library().dm_probe_atomic_rates(r.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream))
+    if rc != 0:
+        raise DemapError(rc, "dm_probe_atomic_rates failed")
+    return {"one_address_per_s": r[0], "spread_per_s": r[1], "spread_addresses": int(r[2])}
 
 
 def profile_enable(on: bool = True):

@@ -106,6 +106,60 @@ extern "C" int dm_probe_valu_rates(double* rates, void* stream) {
     return 0;
 }
 
+// ---- device-scope atomics on one address and spread over the fix-up queue's counters ----
+namespace {
+
+constexpr int kAtomThreads = 1024;
+constexpr int kAtomPerWave = 32;
+constexpr int kAtomAddrs = 64;    // as many addresses as the fix-up queue has counters
+constexpr int kAtomStride = 64;   // words between two of them, as in the queue
+
+// Lane 0 of every wave adds kAtomPerWave times to counter (global wave index) % naddr.
+__global__ __launch_bounds__(kAtomThreads) void probe_atomics(unsigned int* ctr, int naddr) {
+    const unsigned int w = blockIdx.x * (kAtomThreads / 64) + (threadIdx.x >> 6);
+    unsigned int* c = ctr + (size_t)(w % (unsigned int)naddr) * kAtomStride;
+    if ((threadIdx.x & 63) == 0)
+        for (int i = 0; i < kAtomPerWave; ++i) atomicAdd(c, 1u);
+}
+
+double time_atomics(unsigned int* ctr, int naddr, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    hipLaunchKernelGGL(probe_atomics, dim3(grid), dim3(kAtomThreads), 0, st, ctr, naddr);  // warm-up
+    hipEventRecord(e0, st);
+    hipLaunchKernelGGL(probe_atomics, dim3(grid), dim3(kAtomThreads), 0, st, ctr, naddr);
+    hipEventRecord(e1, st);
+    hipEventSynchronize(e1);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, e0, e1);
+    return (double)ms * 1e-3;
+}
+
+}  // namespace
+
+extern "C" int dm_probe_atomic_rates(double* rates, void* stream) {
+    if (!rates) return -1;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -3;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -3;
+    unsigned int* ctr = nullptr;
+    if (hipMalloc(&ctr, sizeof(unsigned int) * kAtomAddrs * kAtomStride) != hipSuccess) return -4;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const double n = (double)cus * (kAtomThreads / 64) * kAtomPerWave;
+    const double t_one = time_atomics(ctr, 1, cus, st, e0, e1);
+    const double t_spread = time_atomics(ctr, kAtomAddrs, cus, st, e0, e1);
+    hipError_t err = hipGetLastError();
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(ctr);
+    if (err != hipSuccess) return -3;
+    rates[0] = n / t_one;     // atomics per second, all on one address
+    rates[1] = n / t_spread;  // atomics per second over kAtomAddrs addresses
+    rates[2] = (double)kAtomAddrs;
+    return 0;
+}
+
 // ---- MFMA lane-layout check (gfx950): one 32x32x16 or 16x16x32 product with the fragment
 // mapping the demapping kernels assume, so a test can compare it with A @ B on the host.
 namespace {

@@ -49,6 +49,15 @@ def test_mfma_lane_layout(dtype, shape):
     assert np.array_equal(D, A @ B)
 
 
+def test_atomic_probe_rates():
+    # both rates finite and positive; the same atomics spread over the queue's 64 counters are
+    # not slower than on one address
+    r = dm.probe_atomic_rates()
+    assert r["spread_addresses"] == 64
+    assert 0.0 < r["one_address_per_s"] < math.inf and 0.0 < r["spread_per_s"] < math.inf
+    assert r["spread_per_s"] >= r["one_address_per_s"]
+
+
 def _run_prec(name, N, prec, snr_sel=None):
     w = W.workload(name, N=N)
     tx, z = W.workload_tx_noise(w)
