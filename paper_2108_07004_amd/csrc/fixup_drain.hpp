@@ -189,12 +189,15 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
         // counting sort of the chunk by key = low 8 mask bits
         s_bin[tid] = 0u;
         __syncthreads();
-        const bool have = (uint32_t)tid < nc;
         FixEntry mine{};
         uint32_t key = 0u;
-        if (have) {
+        bool have = false;  // an entry with bits left to recompute
+        if ((uint32_t)tid < nc) {
             mine = fetch(c0 + tid);
             count_pairs(mine);
+            have = (mine.mask & (0xFFFFu | kMiFlag)) != 0u;
+        }
+        if (have) {
             key = mine.mask & 0xFFu;
             atomicAdd(&s_bin[key], 1u);
         }
@@ -208,15 +211,18 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
         }
         if (lane == 63) s_wsum[wv] = x;
         __syncthreads();
-        uint32_t pre = 0u;
-        for (int w = 0; w < wv; ++w) pre += s_wsum[w];
+        uint32_t pre = 0u, nl = 0u;  // nl: entries dealt out as rows
+        for (int w = 0; w < kFixSortChunk / 64; ++w) {
+            if (w < wv) pre += s_wsum[w];
+            nl += s_wsum[w];
+        }
         s_bin[tid] = x + pre - own;  // exclusive start of bin tid
         __syncthreads();
         if (have) s_sorted[atomicAdd(&s_bin[key], 1u)] = mine;
         __syncthreads();
-        for (uint32_t base = (uint32_t)wv * 4; base < nc; base += (blockDim.x >> 6) * 4) {  // uniform over the wave
+        for (uint32_t base = (uint32_t)wv * 4; base < nl; base += (blockDim.x >> 6) * 4) {  // uniform over the wave
             const uint32_t i = base + (uint32_t)(lane >> 4);
-            const bool live = i < nc;
+            const bool live = i < nl;
             const FixEntry e = s_sorted[live ? i : base];  // a spare row repeats a valid entry, masked off
             const uint32_t mask = live ? e.mask : 0u;
             const float near_lse = __builtin_bit_cast(float, e.near);
@@ -336,6 +342,33 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
     }
 }
 
+// Exclusive prefix of the queue regions' fill into s_qpre[0 .. kQueueRegions]: wave 0 of the
+// block computes it; the caller synchronises the block before reading it.
+__device__ __forceinline__ void queue_prefix(const Sinks& k, uint32_t* s_qpre) {
+    static_assert(kQueueRegions == 64, "one wave scans the region counts");
+    if (threadIdx.x < 64) {  // wave 0, fully active
+        const int r = threadIdx.x;
+        uint32_t x = min(k.queue_count[r * kQueueStride], k.queue_cap / kQueueRegions);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (r >= off) x += y;
+        }
+        s_qpre[r + 1] = x;
+        if (r == 0) s_qpre[0] = 0u;
+    }
+}
+
+// Position in k.queue of entry i < s_qpre[kQueueRegions] of the filled regions read as one list:
+// the largest region r with s_qpre[r] <= i holds it at offset i - s_qpre[r].
+__device__ __forceinline__ size_t queue_index(const Sinks& k, const uint32_t* s_qpre, uint32_t i) {
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t step = kQueueRegions / 2; step >= 1; step >>= 1)
+        if (s_qpre[r + step] <= i) r += step;
+    return (size_t)r * (k.queue_cap / kQueueRegions) + (i - s_qpre[r]);
+}
+
 // Drain the fix-up queue: symbols of constellations with at most kFixLaneMaxM points are
 // recomputed one per lane (fixup_one: cheaper than wave reductions for so few points), the
 // others one per wavefront (fixup_wave).  view(e) gives the block of a queue entry; tl is the
@@ -355,30 +388,11 @@ __device__ void drain_fix_queue(const Sinks& k, ViewFn view, float* tl, int cach
     __shared__ unsigned long long s_acc[kFixLdsTags * 2];
     __shared__ uint32_t s_pairs[kFixLdsTags];
     __shared__ uint32_t s_qpre[kQueueRegions + 1];  // exclusive prefix of the regions' fill
-    static_assert(kQueueRegions == 64, "one wave scans the region counts");
     for (int i = threadIdx.x; i < kFixLdsTags * 2; i += blockDim.x) s_acc[i] = 0ull;
     for (int i = threadIdx.x; i < kFixLdsTags; i += blockDim.x) s_pairs[i] = 0u;
-    const uint32_t seg = k.queue_cap / kQueueRegions;
-    if (threadIdx.x < 64) {  // wave 0, fully active
-        const int r = threadIdx.x;
-        uint32_t x = min(k.queue_count[r * kQueueStride], seg);
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (r >= off) x += y;
-        }
-        s_qpre[r + 1] = x;
-        if (r == 0) s_qpre[0] = 0u;
-    }
+    queue_prefix(k, s_qpre);
     __syncthreads();
-    // entry i < count: the largest region r with s_qpre[r] <= i holds it at offset i - s_qpre[r]
-    auto fetch = [&](uint32_t i) -> FixEntry {
-        uint32_t r = 0;
-#pragma unroll
-        for (uint32_t step = kQueueRegions / 2; step >= 1; step >>= 1)
-            if (s_qpre[r + step] <= i) r += step;
-        return k.queue[(size_t)r * seg + (i - s_qpre[r])];
-    };
+    auto fetch = [&](uint32_t i) -> FixEntry { return k.queue[queue_index(k, s_qpre, i)]; };
     auto count_pairs = [&](const FixEntry& e) {
         if (!k.fix_pairs) return;
         const uint32_t c = (uint32_t)__popc(e.mask & 0xFFFFu);

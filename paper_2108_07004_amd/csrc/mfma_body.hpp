@@ -303,12 +303,15 @@ __device__ __forceinline__ void mfma_subset_sums(const MfmaAcc& A, int h, float 
 // the per-symbol GMI (both halves) and MI (half 0) terms, from this half's subset sums S0 / S1
 // and total tot.  MB < 16: the constellation has exactly MB label bits (known at compile
 // time); MB == 16: b.m bits.  txl is the symbol's transmitted label (0 without tx), loaded by
-// the caller before the tile loop so that its latency is hidden.
+// the caller before the tile loop so that its latency is hidden.  With a non-null defer the
+// flagged bits are not queued: *defer receives the symbol's fix-up mask (both halves) and
+// defer_near its FixEntry.near word, for the caller to resolve or queue.
 template <typename T, int D, bool SPLIT, int MB>
 __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, const uint16_t* pv,
                                             const Frags<T, Slots<D, SPLIT>::S>& bfr, const float (&S0)[MB],
                                             const float (&S1)[MB], float tot, int64_t n, bool active, bool bad,
-                                            int txl, int lane, float& g, float& mi) {
+                                            int txl, int lane, float& g, float& mi, uint32_t* defer = nullptr,
+                                            uint32_t* defer_near = nullptr) {
     using V = typename Mma<T>::V;
     constexpr int S = Slots<D, SPLIT>::S;
     constexpr int NJ = (MB + 1) / 2;
@@ -441,6 +444,11 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
         }
     }
     mask = half_or(mask);
+    if (defer) {
+        *defer = mask;
+        *defer_near = near_word(stot, m, bad_sym);
+        return;
+    }
     if (mask && active && h == 0) {
         double gc = 0.0, mc = 0.0;
         queue_or_fix<D>(b, k, (uint32_t)n, mask, near_word(stot, m, bad_sym), gc, mc);

@@ -56,6 +56,10 @@ __device__ __forceinline__ void mfma_small_sums(const uint4* lds_frag, int lane,
         for (int q = 0; q < 16; ++q) accA[q] = t == 0 ? e[q] : accA[q] + e[q];
         tt[t] = (((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]))) +
                 (((e[8] + e[9]) + (e[10] + e[11])) + ((e[12] + e[13]) + (e[14] + e[15])));
+        // One tile in flight at a time: the tile's exponentials are complete here and the next
+        // tiles' LDS reads stay below (a memory clobber), so the compiler cannot issue every
+        // tile's MFMAs up front (16 live accumulators per tile), which spills.
+        asm volatile("" : "+v"(tt[t])::"memory");
     }
     // Bits 0-3 from the register-indexed sums, bit 4 the lane half, bits 5 and up from the tile
     // totals (tile index bit i = label bit 5 + i).
