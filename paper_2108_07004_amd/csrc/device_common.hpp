@@ -203,16 +203,14 @@ __device__ __forceinline__ float gmi_bit_term(float L, int tx_bit) {
 }
 
 // LLR in log2 units and the per-bit GMI term from the two subset sums (positive, normal):
-// L = log2 s1 - log2 s0 and g = 1 - log2((s0 + s1) / s_b), s_b the transmitted bit's sum.
-// Both use the exact binary exponents and O(1) mantissa logs, so the GMI term needs no exp2:
-// when s_b dominates, s0 + s1 and s_b share their exponent and the mantissa logs differ by
-// the small true value.
-__device__ __forceinline__ float llr_gmi(float s0, float s1, int tx_bit, float& g) {
+// L = log2 s1 - log2 s0 and g = 1 - log2(S / s_b), s_b the transmitted bit's sum and S the
+// symbol's total (the same for every bit: s0 + s1 = S), whose binary exponent es and mantissa
+// log ls the caller forms once per symbol.  Both use the exact binary exponents and O(1)
+// mantissa logs, so the GMI term needs no exp2: when s_b dominates, S and s_b share their
+// exponent and the mantissa logs differ by the small true value.
+__device__ __forceinline__ float llr_gmi(float s0, float s1, int tx_bit, int es, float ls, float& g) {
     const int e0 = __builtin_amdgcn_frexp_expf(s0), e1 = __builtin_amdgcn_frexp_expf(s1);
     const float l0 = hw_log2(__builtin_amdgcn_frexp_mantf(s0)), l1 = hw_log2(__builtin_amdgcn_frexp_mantf(s1));
-    const float ss = s0 + s1;
-    const int es = __builtin_amdgcn_frexp_expf(ss);
-    const float ls = hw_log2(__builtin_amdgcn_frexp_mantf(ss));
     const int eb = tx_bit ? e1 : e0;
     const float lb = tx_bit ? l1 : l0;
     g = 1.0f - ((float)(es - eb) + (ls - lb));

@@ -347,6 +347,9 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
     asm volatile("" : "+v"(hv));
     uint32_t flagged = 0;
     float Lv[NJ];
+    // the symbol's total, shared by every bit's GMI term (s0 + s1 = stot)
+    const int es = __builtin_amdgcn_frexp_expf(stot);
+    const float ls = hw_log2(__builtin_amdgcn_frexp_mantf(stot));
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         if (2 * j < m) {
@@ -356,7 +359,7 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
             const uint32_t u0 = __builtin_bit_cast(uint32_t, s0), u1 = __builtin_bit_cast(uint32_t, s1);
             const bool ok = !bad_sym && min(u0, u1) >= lo_u && max(u0, u1) < hi_u;
             float gb;
-            Lv[j] = llr_gmi(s0, s1, (txl >> p) & 1, gb) * 0.69314718055994531f;
+            Lv[j] = llr_gmi(s0, s1, (txl >> p) & 1, es, ls, gb) * 0.69314718055994531f;
             g += (valid && ok) ? gb : 0.0f;
             flagged |= (valid && !ok) ? 1u << p : 0u;
         }
