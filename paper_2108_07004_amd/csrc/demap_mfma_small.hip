@@ -101,45 +101,9 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
         uint32_t mask, near;
         mfma_finish<T, D, SPLIT, MB>(b, k, reinterpret_cast<const uint16_t*>(lds_pv), bfr, S0, S1, tot, n, active, bad,
                                      txl, lane, g, mi, &mask, &near);
-        // Far-subset pass: a flagged bit whose symbol passed its near log-sum has a far subset
-        // whose terms all lie below the flag bound sh = m - 102.  The same 32 symbols run the
-        // tile loop again with the exponent offset lowered by sh: every far term is then kept to
-        // FP32 precision down to 2^-126, while near terms overflow to +inf -- harmlessly, since
-        // every register-indexed sum and tile total that makes up a far subset holds far terms
-        // only.  L = (sh + log2 S_far) - (near log-sum) with the sign of the far side, the same
-        // exponent arithmetic as every other LLR of the precision.  A far sum under 2^-95 (where
-        // flushed terms could matter) leaves its bit to the fix-up queue, as do symbols without
-        // the near log-sum and the MI term.  At high SNR nearly every batch takes this pass; it
-        // replaces a queue entry and a recomputation from the queue per such symbol.
-        constexpr float sh = (float)(MB - 102);
-        constexpr uint32_t kFarMask = (1u << (MB < kFarBits ? MB : kFarBits)) - 1u;
-        const uint32_t far = (active && near != kNearNone) ? (mask & kFarMask) : 0u;
-        if (__ballot(far != 0u) != 0ull) {  // uniform per wave
-            bool bad2 = false;
-            const Frags<T, S> bfr2 = build_symbol_frags<T, D, SPLIT>(y, b.c, b.K - sh, h, bad2);
-            mfma_small_sums<T, D, SPLIT, NT>(lds_frag, lane, bfr2, S0, S1, tot);
-            const bool bad_sym = half_or((uint32_t)(bad || bad2)) != 0;
-            const float near_lse = __builtin_bit_cast(float, near);
-            uint32_t done = 0u;
-#pragma unroll
-            for (int j = 0; j < (MB + 1) / 2; ++j) {
-                const float c0 = half_pair_sum(S0[2 * j], 2 * j + 1 < MB ? S0[2 * j + 1] : 0.0f);
-                const float c1 = half_pair_sum(S1[2 * j], 2 * j + 1 < MB ? S1[2 * j + 1] : 0.0f);
-                const int p = 2 * j + h;
-                if (p < MB && ((far >> p) & 1u) && !bad_sym) {
-                    const int fb = (int)((mask >> (kFarShift + p)) & 1u);
-                    const float sf = fb ? c1 : c0;
-                    if (sf >= 0x1p-95f && sf < 3.0e38f) {
-                        const float lf = sh + hw_log2(sf);
-                        const float L = fb ? lf - near_lse : near_lse - lf;
-                        if (b.llr) b.llr[(size_t)n * MB + (MB - 1 - p)] = L * 0.69314718055994531f;
-                        if (b.tx) g += gmi_bit_term(L, (txl >> p) & 1);
-                        done |= 1u << p;
-                    }
-                }
-            }
-            mask &= ~half_or(done);
-        }
+        // far subsets of flagged bits resolved in the wave (at high SNR nearly every batch has
+        // some; each would otherwise be a queue entry and a recomputation from the queue)
+        mfma_small_far_pass<T, D, SPLIT, NT>(lds_frag, lane, y, b.c, b.K, bad, b, n, active, txl, near, mask, g);
         if (mask && active && h == 0) {
             double gc = 0.0, mc = 0.0;
             queue_or_fix<D>(b, k, (uint32_t)n, mask, near, gc, mc);

@@ -98,4 +98,55 @@ __device__ __forceinline__ void mfma_small_sums(const uint4* lds_frag, int lane,
     }
 }
 
+// Far-subset pass of an NT-tile constellation's 32-symbol batch (both lane halves of every
+// symbol call it; uniform per wave).  mask / near: the symbol's fix-up mask and near word from
+// mfma_finish (deferred); y, c, K: the symbol and its block's exponent scale and offset.  A
+// flagged bit whose symbol passed its near log-sum has a far subset whose terms all lie below
+// the flag bound sh = m - 102, so the batch runs the tile loop again with the exponent offset
+// lowered by sh: every far term is then kept to FP32 precision down to 2^-126, while near terms
+// overflow to +inf -- harmlessly, since every register-indexed sum and tile total that makes up
+// a far subset holds far terms only.  L = (sh + log2 S_far) - (near log-sum) with the sign of the
+// far side, the same exponent arithmetic as every other LLR of the precision; the LLR is
+// written, its GMI term added to g and the bit cleared from mask.  A far sum under 2^-95 (where
+// flushed terms could matter) leaves its bit in mask for the fix-up queue, as do symbols
+// without the near log-sum and the MI term.
+template <typename T, int D, bool SPLIT, int NT>
+__device__ __forceinline__ void mfma_small_far_pass(const uint4* lds_frag, int lane, const float (&y)[D], float c,
+                                                    float K, bool bad, const BlockView& b, int64_t n, bool active,
+                                                    int txl, uint32_t near, uint32_t& mask, float& g) {
+    constexpr int MB = SmallBits<NT>::MB;
+    constexpr int S = Slots<D, SPLIT>::S;
+    constexpr float sh = (float)(MB - 102);
+    constexpr uint32_t kFarMask = (1u << (MB < kFarBits ? MB : kFarBits)) - 1u;
+    const uint32_t far = (active && near != kNearNone) ? (mask & kFarMask) : 0u;
+    if (__ballot(far != 0u) == 0ull) return;  // uniform per wave
+    const int h = lane >> 5;
+    bool bad2 = false;
+    const Frags<T, S> bfr2 = build_symbol_frags<T, D, SPLIT>(y, c, K - sh, h, bad2);
+    float S0[MB], S1[MB], tot;
+    mfma_small_sums<T, D, SPLIT, NT>(lds_frag, lane, bfr2, S0, S1, tot);
+    const bool bad_sym = half_or((uint32_t)(bad || bad2)) != 0;
+    const float near_lse = __builtin_bit_cast(float, near);
+    uint32_t done = 0u;
+#pragma unroll
+    for (int j = 0; j < (MB + 1) / 2; ++j) {
+        // lane half h finishes bit 2j + h (the halves' partial sums meet in one swap)
+        const float c0 = half_pair_sum(S0[2 * j], 2 * j + 1 < MB ? S0[2 * j + 1] : 0.0f);
+        const float c1 = half_pair_sum(S1[2 * j], 2 * j + 1 < MB ? S1[2 * j + 1] : 0.0f);
+        const int p = 2 * j + h;
+        if (p < MB && ((far >> p) & 1u) && !bad_sym) {
+            const int fb = (int)((mask >> (kFarShift + p)) & 1u);
+            const float sf = fb ? c1 : c0;
+            if (sf >= 0x1p-95f && sf < 3.0e38f) {
+                const float lf = sh + hw_log2(sf);
+                const float L = fb ? lf - near_lse : near_lse - lf;
+                if (b.llr) b.llr[(size_t)n * MB + (MB - 1 - p)] = L * 0.69314718055994531f;
+                if (b.tx) g += gmi_bit_term(L, (txl >> p) & 1);
+                done |= 1u << p;
+            }
+        }
+    }
+    mask &= ~half_or(done);
+}
+
 }  // namespace dm
