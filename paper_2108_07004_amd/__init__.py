@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = ["Constellation", "DemapError", "MLP", "PREC", "Plan", "demap_batched", "demap_learned", "demap_llr",
            "demap_llr_var", "gmi_estimate", "gs_optimize", "hard_decision", "q_factor_db", "Streamer", "last_fixup_count", "library_path", "load_library", "mlp_param_count",
-           "probe_valu_rates", "probe_atomic_rates", "profile_enable", "profile_read"]
+           "probe_valu_rates", "probe_atomic_rates", "probe_gelu", "profile_enable", "profile_read"]
 
 _LIB_PATH = Path(__file__).resolve().with_name("libdemap.so")
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}
@@ -62,6 +62,8 @@ def load_library():
     lib.dm_probe_valu_rates.restype = I
     lib.dm_probe_atomic_rates.argtypes = [P, P]
     lib.dm_probe_atomic_rates.restype = I
+    lib.dm_probe_gelu.argtypes = [P, P, ctypes.c_int64]
+    lib.dm_probe_gelu.restype = I
     lib.dm_profile_enable.argtypes = [I]
     lib.dm_profile_enable.restype = I
     lib.dm_profile_read.argtypes = [P, P, P, I]
@@ -263,6 +265,18 @@ def probe_atomic_rates(stream=None) -> dict:
     if rc != 0:
         raise DemapError(rc, "dm_probe_atomic_rates failed")
     return {"one_address_per_s": r[0], "spread_per_s": r[1], "spread_addresses": int(r[2])}
+
+
+def probe_gelu(x) -> np.ndarray:
+    """The inference kernel's packed-FP16 GELU on host values x (dm_probe_gelu): FP16 results
+    widened to FP32."""
+    xs = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    out = np.empty_like(xs)
+    rc = load_library().dm_probe_gelu(xs.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p),
+                                      xs.size)
+    if rc != 0:
+        raise DemapError(rc, "dm_probe_gelu failed")
+    return out.reshape(np.shape(x))
 
 
 def profile_enable(on: bool = True):

@@ -1,6 +1,9 @@
-// Fused inference of the learned demapper (gfx950): all BF16 weights (152 KiB of MFMA operand
+// Fused inference of the learned demapper (gfx950): all weights (152 KiB of MFMA operand
 // fragments + FP32 biases) live in LDS; each wavefront runs 32 received symbols through the
-// three layers on v_mfma_f32_32x32x16_bf16 and writes LLRs and per-symbol GMI terms.
+// three layers on v_mfma_f32_32x32x16 and writes LLRs and per-symbol GMI terms.  Layer 1 takes
+// BF16 operands (features and W1 as trained); the GELU of its outputs and of layer 2's is
+// evaluated two values at a time in packed FP16 (gelu2 below) and feeds layers 2 and 3 as FP16
+// operands, W2 and W3 being converted from their BF16 values (exactly, above 2^-14).
 //
 // Hidden units are permuted so that no activation has to move between lanes: the A operand
 // of output block b (32 units) has in row i the unit
@@ -13,6 +16,7 @@
 // pair, ~16 significant bits; b2 and b3 sit in LDS in the permuted order, FP32.
 #include <hip/hip_runtime.h>
 
+#include "../../include/demap_probe.h"
 #include "device_common.hpp"
 #include "mlp_kernels.hpp"
 
@@ -21,6 +25,8 @@ namespace dm {
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kH = 256;
@@ -39,21 +45,50 @@ __device__ __forceinline__ int perm_unit(int b, int i) {
     return 32 * b + 16 * (r >> 3) + 8 * h + (r & 7);
 }
 
-// tanh-form GELU, 0.5 x (1 + tanh(u)) = x / (1 + exp(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3).
-// exp(-2u) = 2^(x (c0 + c1 x^2)) with c0 = -2 sqrt(2/pi) log2(e), c1 = 0.044715 c0: three
-// multiply-adds, exp2, add, reciprocal, multiply per element.
-__device__ __forceinline__ float gelu_f(float x) {
-    const float t = fmaf(-0.10294324f, x * x, -2.3022082f);
-    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * t));
+// The tanh-form GELU x Phi(x), Phi(x) = (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))) / 2, of two
+// values at once in packed FP16 with no transcendental: with v = clamp(x / 6 + 1/2, 0, 1) and
+// u = 2 v - 1 (x / 3 clamped to [-1, 1]),
+//     Phi(x) ~ clamp(1/2 + u P(u^2), 0, 1),  P(s) = p0 + p1 s + p2 s^2 + p3 s^3 + p4 s^4,
+// P a near-minimax fit of (Phi - 1/2) / u on [0, 3]; each step below is one packed FP16
+// operation (the multiply-adds rounded once, the clamps folded into them).  The two inputs are
+// converted rounding toward zero, which saturates at the FP16 maximum 65504 instead of
+// overflowing.  Over every finite FP16 input the result stays within 1.2e-3 of Phi (checked
+// exhaustively on the GPU through dm_probe_gelu against the FP64 tanh form; the fit alone is
+// within 2.8e-4 on [-3, 3], and Phi(-3) = 1.3e-3 bounds the clamped tails), and the product
+// x Phi is rounded to FP16 once more.  Per pair of values that is 10 full-rate instructions;
+// the exact form's exp2 and reciprocal alone take four issue cycles each per value.
+__device__ __forceinline__ f16x2 gelu2(float a, float b) {
+    const f16x2 x = __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(a, b));
+    const f16x2 zero = (f16x2)(_Float16)0.0f, one = (f16x2)(_Float16)1.0f;
+    const f16x2 v = __builtin_elementwise_min(
+        __builtin_elementwise_max(__builtin_elementwise_fma(x, (f16x2)(_Float16)(1.0f / 6.0f), (f16x2)(_Float16)0.5f), zero),
+        one);
+    const f16x2 u = __builtin_elementwise_fma(v, (f16x2)(_Float16)2.0f, (f16x2)(_Float16)-1.0f);
+    const f16x2 s = u * u;
+    f16x2 p = (f16x2)(_Float16)0.393552818f;
+    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)-1.356858143f);
+    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)1.999497139f);
+    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)-1.730723903f);
+    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)1.193597265f);
+    const f16x2 ph = __builtin_elementwise_min(
+        __builtin_elementwise_max(__builtin_elementwise_fma(u, p, (f16x2)(_Float16)0.5f), zero), one);
+    return x * ph;
 }
 
 // Fragment table from row-major (out x in) BF16 weights: W1t [256 x 32] (inputs 0..13 used),
 // W2t [256 x 256], W3t [32 x 256]; the FP32 layer-1 bias b1 becomes input columns 14 (hi) and
-// 15 (lo).  One thread per fragment.
+// 15 (lo).  W1 stays BF16; W2 and W3 become FP16 operands, exactly for magnitudes in
+// [2^-14, 65504], to within 2^-25 below that, saturated at 65504 above it.  One thread per
+// fragment.
+__device__ __forceinline__ _Float16 to_f16_sat(__bf16 w) {
+    return (_Float16)fminf(fmaxf((float)w, -65504.0f), 65504.0f);
+}
+
 __global__ void pack_kernel(const __bf16* W1t, const __bf16* W2t, const __bf16* W3t, const float* b1, uint4* frag) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= kFrags) return;
     __bf16 v[8];
+    _Float16 w[8];
     if (f < kW1Frags) {
         const int b = f / 64, l = f % 64;
         const int u = perm_unit(b, l % 32);
@@ -67,12 +102,16 @@ __global__ void pack_kernel(const __bf16* W1t, const __bf16* W2t, const __bf16* 
         const int g = f - kW1Frags;
         const int b = g / (16 * 64), t = (g / 64) % 16, l = g % 64;
         const int u = perm_unit(b, l % 32);
-        for (int q = 0; q < 8; ++q) v[q] = W2t[u * kH + 16 * t + 8 * (l / 32) + q];
+        for (int q = 0; q < 8; ++q) w[q] = to_f16_sat(W2t[u * kH + 16 * t + 8 * (l / 32) + q]);
+        frag[f] = *reinterpret_cast<const uint4*>(w);
+        return;
     } else {
         const int g = f - kW1Frags - kW2Frags;
         const int t = g / 64, l = g % 64;
         const int o = l % 32;
-        for (int q = 0; q < 8; ++q) v[q] = W3t[o * kH + 16 * t + 8 * (l / 32) + q];
+        for (int q = 0; q < 8; ++q) w[q] = to_f16_sat(W3t[o * kH + 16 * t + 8 * (l / 32) + q]);
+        frag[f] = *reinterpret_cast<const uint4*>(w);
+        return;
     }
     frag[f] = *reinterpret_cast<const uint4*>(v);
 }
@@ -114,13 +153,17 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
             else if (k >= 14) v = 1.0f;
             xf[q] = (__bf16)v;
         }
-        bf16x8 a1[16];
+        f16x8 a1[16];
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                 __builtin_bit_cast(bf16x8, w1[b * 64 + lane]), xf, f32x16{}, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) a1[2 * b + (r >> 3)][r & 7] = (__bf16)gelu_f(acc[r]);
+            for (int r = 0; r < 16; r += 2) {
+                const f16x2 g2 = gelu2(acc[r], acc[r + 1]);
+                a1[2 * b + (r >> 3)][r & 7] = g2[0];
+                a1[2 * b + (r >> 3)][(r & 7) + 1] = g2[1];
+            }
         }
         f32x16 acc3 = {};
         // Layer-2 weight fragments stream through a ring of kRing registers: the read of
@@ -130,14 +173,14 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
         // blocks: while the 16 MFMAs of block b run, the wave evaluates block b-1's 16 GELUs, one
         // per MFMA, and feeds them to layer 3 afterwards, so matrix and vector work overlap
         // within the wave.
-        bf16x8 ring[kRing];
+        f16x8 ring[kRing];
 #pragma unroll
-        for (int q = 0; q < kRing; ++q) ring[q] = __builtin_bit_cast(bf16x8, w2[q * 64 + lane]);
+        for (int q = 0; q < kRing; ++q) ring[q] = __builtin_bit_cast(f16x8, w2[q * 64 + lane]);
         auto l2_step = [&](int b, int ks, f32x16 acc) {
-            const bf16x8 cur = ring[ks % kRing];
+            const f16x8 cur = ring[ks % kRing];
             const int next = min(b * 16 + ks + kRing, 8 * 16 - 1);
-            ring[ks % kRing] = __builtin_bit_cast(bf16x8, w2[next * 64 + lane]);
-            return __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur, a1[ks], acc, 0, 0, 0);
+            ring[ks % kRing] = __builtin_bit_cast(f16x8, w2[next * 64 + lane]);
+            return __builtin_amdgcn_mfma_f32_32x32x16_f16(cur, a1[ks], acc, 0, 0, 0);
         };
         // Block p's layer-2 biases seed its accumulators (the MFMAs add onto them).
         auto bias_acc = [&](int p) {
@@ -161,18 +204,25 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
         }
         // block p's GELUs feed layer 3; with `next` the MFMAs of block p + 1 run in between
         auto finish = [&](int p, bool next, f32x16& accn) {
-            const bf16x8 w3lo = __builtin_bit_cast(bf16x8, w3[(2 * p) * 64 + lane]);
-            const bf16x8 w3hi = __builtin_bit_cast(bf16x8, w3[(2 * p + 1) * 64 + lane]);
-            bf16x8 lo, hi;
+            const f16x8 w3lo = __builtin_bit_cast(f16x8, w3[(2 * p) * 64 + lane]);
+            const f16x8 w3hi = __builtin_bit_cast(f16x8, w3[(2 * p + 1) * 64 + lane]);
+            f16x8 lo, hi;
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks) {
                 if (next) accn = l2_step(p + 1, ks, accn);
-                const __bf16 q = (__bf16)gelu_f(accp[ks]);
-                if (ks < 8) lo[ks] = q;
-                else hi[ks - 8] = q;
+                if (ks & 1) {
+                    const f16x2 g2 = gelu2(accp[ks - 1], accp[ks]);
+                    if (ks < 8) {
+                        lo[ks - 1] = g2[0];
+                        lo[ks] = g2[1];
+                    } else {
+                        hi[ks - 9] = g2[0];
+                        hi[ks - 8] = g2[1];
+                    }
+                }
             }
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3lo, lo, acc3, 0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3hi, hi, acc3, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w3lo, lo, acc3, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w3hi, hi, acc3, 0, 0, 0);
         };
 #pragma unroll 1
         for (int b = 1; b < 8; ++b) {
@@ -210,6 +260,14 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
     if (a.acc && lane == 0) acc_add(a.acc, 0, slot, 0, gsum);
 }
 
+__global__ void probe_gelu_kernel(const float* x, float* out, int64_t n) {
+    const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const f16x2 g = gelu2(x[i], i + 1 < n ? x[i + 1] : 0.0f);
+    out[i] = (float)g[0];
+    if (i + 1 < n) out[i + 1] = (float)g[1];
+}
+
 }  // namespace
 
 size_t mlp_frag_count() { return kFrags; }
@@ -230,3 +288,23 @@ hipError_t launch_mlp_infer(const MlpInferArgs& a, int grid, hipStream_t st) {
 }
 
 }  // namespace dm
+
+extern "C" int dm_probe_gelu(const float* x, float* out, int64_t n) {
+    if (n < 0 || n > (int64_t(1) << 24) || (n > 0 && (!x || !out))) return -1;
+    if (n == 0) return 0;
+    float *dx = nullptr, *dy = nullptr;
+    if (hipMalloc(&dx, n * 4) != hipSuccess || hipMalloc(&dy, n * 4) != hipSuccess) {
+        hipFree(dx);
+        return -4;
+    }
+    hipError_t e = hipMemcpy(dx, x, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const int64_t pairs = (n + 1) / 2;
+        hipLaunchKernelGGL(dm::probe_gelu_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, 0, dx, dy, n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dy, n * 4, hipMemcpyDeviceToHost);
+    hipFree(dx);
+    hipFree(dy);
+    return e == hipSuccess ? 0 : -3;
+}

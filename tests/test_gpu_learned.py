@@ -7,10 +7,13 @@
   points emulated (activations and deltas as BF16 hi + lo pairs): cosine >= 0.99999, max
   error <= 2e-3 RMS.
 * Adam's first step against its closed form -lr g / (|g| + eps), g the GPU gradient.
+* The inference kernel's packed-FP16 GELU on every finite FP16 input against the FP64 tanh form:
+  x Phi(x) with Phi within EPS_PHI = 1.2e-3, plus the final FP16 rounding.
 * Fused inference (LLRs and GMI) against the oracle network with BF16-rounded weights and
-  inputs only, element by element within a first-order bound derived from the kernel's operand
-  precision (BF16 activations, the layer-1 bias as a BF16 pair, FP32 accumulation); and, as a
-  diagnostic, against the oracle with the kernel's storage points emulated.
+  inputs only, element by element within a first-order bound derived from the kernel's
+  arithmetic (BF16 first layer with its bias as a BF16 pair, the GELU above, FP16 layer-2 and
+  layer-3 operands, FP32 accumulation); and, as a diagnostic, against the oracle with the
+  kernel's storage points emulated (FP16 activations of the exact GELU).
 * Every fallback reason, and that fallback results are the exact path's.
 * Training a 2D 16-point constellation brings the learned GMI close to the exact GMI, training an
   8D M = 2048 Gray product constellation passes the 0.01-bit audit at every SNR, and two
@@ -142,31 +145,68 @@ def test_adam_first_step_closed_form():
         assert np.all(err <= bound), (k, float(np.max(err / bound)))
 
 
+def _f16_round(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
 def _infer_ref(w, y, sigma2):
-    """Oracle forward with the inference kernel's storage: BF16 weights, inputs and activations,
-    the first-layer bias as a BF16 hi + lo pair (diagnostic)."""
+    """Oracle forward with the inference kernel's storage: BF16 weights and inputs, the
+    first-layer bias as a BF16 hi + lo pair, FP16 activations of the exact GELU (diagnostic)."""
     b1 = np.asarray(w["b1"], dtype=np.float32)
     hi = mlp.bf16_round(b1)
     lo = mlp.bf16_round((b1 - hi.astype(np.float32)).astype(np.float32))
     X = mlp.features(y, _snr_of(sigma2))
-    out, _ = mlp.forward_stored(_w64(w), X, b1=hi + lo)
+    out, _ = mlp.forward_stored(_w64(w), X, b1=hi + lo, rnd_act=_f16_round)
     return out
 
 
-U_BF16 = 2.0 ** -8      # unit roundoff of BF16 (8 significant bits)
 U_PAIR = 2.0 ** -16     # a value carried as a BF16 hi + lo pair
 U_FP32 = 2.0 ** -24
+U_F16 = 2.0 ** -11      # unit roundoff of FP16 (round to nearest)
+U_F16_RTZ = 2.0 ** -10  # FP16 conversion rounding toward zero
+F16_SUB = 2.0 ** -25    # half the FP16 subnormal spacing (absolute rounding error below 2^-14)
 GELU_LIP = 1.13         # max |GELU'| of the tanh form (1.1289 near x = 1.5)
-U_GELU = 2.0 ** -20     # relative error of the kernel's GELU evaluation (exp2, reciprocal: ~1 ulp each)
+EPS_PHI = 1.2e-3        # design budget of |Phi~ - Phi| for the kernel's packed-FP16 GELU
+
+
+def _gelu_bound(x, out):
+    """Allowed |gelu2(x) - GELU(x)| for FP16 inputs x: EPS_PHI |x| for Phi~, then the product's
+    FP16 rounding (relative 2^-11 of the result, or 2^-25 absolute in the subnormal range)."""
+    return EPS_PHI * np.abs(x) + U_F16 * (1.0 + 2.0 ** -10) * np.abs(out) + F16_SUB
+
+
+def test_inference_gelu_every_fp16_input():
+    h = np.arange(0, 1 << 16, dtype=np.uint32).astype(np.uint16).view(np.float16)
+    h = h[np.isfinite(h)]
+    x = np.concatenate([h, h[:1]]).astype(np.float32)  # odd count: the last pair is half used
+    got = dm.probe_gelu(x).astype(np.float64)
+    x64 = x.astype(np.float64)
+    want = mlp.gelu(x64)
+    err = np.abs(got - want)
+    assert np.all(err <= _gelu_bound(x64, got)), float(np.max(err / _gelu_bound(x64, got)))
+    # Phi's own error where the final rounding is negligible
+    big = np.abs(x64) >= 1.0
+    phi_err = np.max((err[big] - U_F16 * np.abs(got[big])) / np.abs(x64[big]))
+    print(f"packed-FP16 GELU: max |Phi~ - Phi| ~ {phi_err:.3e} over {x.size} FP16 inputs")
+    assert got[np.flatnonzero(h == 0)[0]] == 0.0
+    # inputs beyond the FP16 range saturate (rounding toward zero) instead of overflowing
+    sat = dm.probe_gelu(np.array([1e6, -1e6, 3e38, 65504.0, -65504.0], dtype=np.float32)).astype(np.float64)
+    assert np.all(np.isfinite(sat))
+    assert sat[0] == sat[3] and sat[2] == sat[3] and sat[1] == sat[4]
+    assert dm.probe_gelu(np.zeros(0, np.float32)).size == 0
 
 
 def _infer_bound(w, y, sigma2):
     """The network with BF16-rounded weights and inputs only (activations unrounded) and a
     first-order bound on how far the inference kernel may be from it per output:
-      layer 1:  dh1 <= 2^-16 |b1| + g_9 |X| |W1|            (bias as a BF16 pair, FP32 sums)
-      GELU:     da  <= L dh + (u + 2^-20) |a|                (L = max |GELU'|; a stored as BF16)
-      layer k:  dh  <= |W|^T da + g_256 |W|^T |a|            (FP32 accumulation, g_n = n u32)
-    Returns (out, bound)."""
+      layer 1:  dh1 <= 2^-16 |b1| + g_9 |X| |W1|             (bias as a BF16 pair, FP32 sums)
+      GELU:     da  <= (1 + 2^-9) [L dh + (L 2^-10 + eps) (|h| + dh) + 2^-11 |a|] + 2^-23
+                (input converted to FP16 toward zero, Phi~ within eps, product rounded to FP16;
+                 L = max |GELU'|, 2^-23 covers the subnormal absolute errors)
+      layer k:  dh  <= |W|^T da + 2^-25 sum(|a| + da) + g_256 |W|^T (|a| + da)
+                (W converted to FP16: exact above 2^-14, within 2^-25 below; FP32 accumulation,
+                 g_n = n u32)
+    The pre-activations must stay inside the FP16 range.  Returns (out, bound)."""
     wr = {k: (mlp.bf16_round(v) if k.startswith("W") else np.asarray(v, np.float64)) for k, v in w.items()}
     X = mlp.bf16_round(mlp.features(y, _snr_of(sigma2)))
     h1 = X @ wr["W1"] + wr["b1"]
@@ -174,13 +214,23 @@ def _infer_bound(w, y, sigma2):
     h2 = a1 @ wr["W2"] + wr["b2"]
     a2 = mlp.gelu(h2)
     out = a2 @ wr["W3"] + wr["b3"]
+    assert max(np.max(np.abs(h1)), np.max(np.abs(h2))) < 60000.0
     aW1, aW2, aW3 = (np.abs(wr[k]) for k in ("W1", "W2", "W3"))
     g = lambda n: n * U_FP32 / (1.0 - n * U_FP32)  # noqa: E731
+
+    def act(h, a, dh):
+        return (1.0 + 2.0 ** -9) * (GELU_LIP * dh + (GELU_LIP * U_F16_RTZ + EPS_PHI) * (np.abs(h) + dh)
+                                    + U_F16 * np.abs(a)) + 2.0 ** -23
+
+    def layer(a, da, aW, b):
+        ab = np.abs(a) + da
+        return da @ aW + F16_SUB * ab.sum(axis=1, keepdims=True) + g(257) * (ab @ aW + np.abs(b))
+
     dh1 = U_PAIR * np.abs(wr["b1"]) + g(X.shape[1] + 2) * (np.abs(X) @ aW1 + np.abs(wr["b1"]))
-    da1 = GELU_LIP * dh1 + (U_BF16 + U_GELU) * np.abs(a1)
-    dh2 = da1 @ aW2 + g(257) * (np.abs(a1) @ aW2 + np.abs(wr["b2"]))
-    da2 = GELU_LIP * dh2 + (U_BF16 + U_GELU) * np.abs(a2)
-    dout = da2 @ aW3 + g(257) * (np.abs(a2) @ aW3 + np.abs(wr["b3"]))
+    da1 = act(h1, a1, dh1)
+    dh2 = layer(a1, da1, aW2, wr["b2"])
+    da2 = act(h2, a2, dh2)
+    dout = layer(a2, da2, aW3, wr["b3"])
     return out, dout
 
 
@@ -212,12 +262,13 @@ def test_inference_matches_oracle_forward():
         g_ref = oracle.gmi_from_llr(11, ref, lab)
         g_bound = float(np.mean(np.sum(bound, axis=1))) / np.log(2.0)
         assert abs(gmi[i] - g_ref) <= g_bound + 1e-6, (snr[i], gmi[i], g_ref, g_bound)
-        # diagnostic: the kernel's storage points emulated
+        # diagnostic: the kernel's storage points emulated (exact GELU, so the gap is mostly the
+        # packed-FP16 GELU's Phi error, ~1e-3 of each activation)
         ref_s = _infer_ref(w, ys[i], v)
         rms = float(np.sqrt(np.mean(ref_s * ref_s)))
         mx = float(np.max(np.abs(got - ref_s))) / rms
         print(f"inference snr={snr[i]}: vs emulated storage max err / RMS = {mx:.2e}")
-        assert mx <= 5e-3, (snr[i], mx)
+        assert mx <= 1e-2, (snr[i], mx)
 
 
 def test_inference_without_tx_and_empty_block():
@@ -231,7 +282,7 @@ def test_inference_without_tx_and_empty_block():
     gmi, loss, fb = dm.demap_learned(net, const, [0.05], [_dev(y)], None, [llr])
     assert fb[0] == 0 and np.isnan(gmi[0])
     ref = _infer_ref(net.get_weights(), y, 0.05)
-    assert np.max(np.abs(llr.cpu().numpy() - ref)) <= 5e-3 * np.sqrt(np.mean(ref * ref))
+    assert np.max(np.abs(llr.cpu().numpy() - ref)) <= 1e-2 * np.sqrt(np.mean(ref * ref))
     e = torch.empty((0, 8), device=DEV)
     gmi, loss, fb = dm.demap_learned(net, const, [0.05], [e], torch.empty(0, dtype=torch.int16, device=DEV), None)
     assert np.isnan(gmi[0]) and fb[0] == 0
