@@ -207,8 +207,9 @@ int dm_demap_llr_var(const dm_constellation* c, const float* sigma2, const float
  * MLP (D+1) -> 256 -> 256 -> m with tanh-form GELU, BF16 weights and activations and FP32
  * accumulation in training, whose m outputs estimate the exact LLRs (nats).  Inference keeps
  * the first layer in BF16 and evaluates the GELU in packed FP16 (within 1.2e-3 of the tanh
- * form's Phi in x Phi(x), dm_probe_gelu) feeding FP16 operands to layers 2 and 3; hidden
- * pre-activations beyond the FP16 range saturate at +-65504.  Its inputs are y and the SNR
+ * form's Phi in x Phi(x), dm_probe_gelu) feeding FP16 operands to layers 2 and 3, the hidden
+ * layers on a quarter scale; hidden pre-activations beyond +-262016 saturate and |W3| should
+ * stay below 16376.  Its inputs are y and the SNR
  * feature (s - 7.5) / 7.5 with s = -10 log10(2 sigma2), the SNR in dB of a constellation with
  * unit energy per two real dimensions.  Training minimises the soft binary cross-entropy
  * between sigmoid(output) and sigmoid(exact LLR), averaged over samples and bits, with Adam on

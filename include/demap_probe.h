@@ -59,9 +59,10 @@ int dm_probe_mfma_layout(int dtype, int shape, const float* A, const float* B, f
 /*
  * The learned demapper's inference-time GELU, x Phi(x) with the tanh-form Phi (the network's
  * activation; the learned demapper is a project addition, see demap.h), evaluated by the
- * very routine the inference kernel uses: packed FP16 arithmetic, the input converted to
- * FP16 rounding toward zero (saturating at +-65504), the result an FP16 value returned widened
- * to FP32.  x and out are HOST arrays of n floats; 0 <= n <= 2^24.  Synchronous on the null
+ * very routine the inference kernel uses: packed FP16 arithmetic on the quarter scale, x / 4
+ * converted to FP16 rounding toward zero (saturating at +-65504, i.e. |x| at 262016), the
+ * result 4 times an FP16 value, returned as FP32.  x and out are HOST arrays of n floats;
+ * 0 <= n <= 2^24.  Synchronous on the null
  * stream.  For checking that evaluation's error over every FP16 input.
  * Returns 0, -1 (bad argument), -3 (HIP error), -4 (allocation failed).
  */

@@ -5,6 +5,12 @@
 // evaluated two values at a time in packed FP16 (gelu2 below) and feeds layers 2 and 3 as FP16
 // operands, W2 and W3 being converted from their BF16 values (exactly, above 2^-14).
 //
+// The hidden layers run on a quarter scale: W1, b1 and b2 are stored divided by 4 and W3
+// multiplied by 4 (exact power-of-two scalings), so each hidden MFMA yields u = h / 4, the GELU
+// step returns u Phi(4u) = GELU(h) / 4, and the next layer's operands absorb the factors: layer
+// 2 computes W2 (a1 / 4) + b2 / 4 = h2 / 4 and layer 3 (4 W3)(a2 / 4) + b3.  The GELU then needs
+// no scaling multiply of its own.
+//
 // Hidden units are permuted so that no activation has to move between lanes: the A operand
 // of output block b (32 units) has in row i the unit
 //     u(b, i) = 32 b + 16 (r / 8) + 8 h + (r % 8),  r = 4 (i / 8) + (i % 4),  h = (i / 4) % 2,
@@ -27,6 +33,7 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kH = 256;
@@ -45,43 +52,55 @@ __device__ __forceinline__ int perm_unit(int b, int i) {
     return 32 * b + 16 * (r >> 3) + 8 * h + (r & 7);
 }
 
-// The tanh-form GELU x Phi(x), Phi(x) = (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))) / 2, of two
-// values at once in packed FP16 with no transcendental: with v = clamp(x / 6 + 1/2, 0, 1) and
-// u = 2 v - 1 (x / 3 clamped to [-1, 1]),
-//     Phi(x) ~ clamp(1/2 + u P(u^2), 0, 1),  P(s) = p0 + p1 s + p2 s^2 + p3 s^3 + p4 s^4,
-// P a near-minimax fit of (Phi - 1/2) / u on [0, 3]; each step below is one packed FP16
-// operation (the multiply-adds rounded once, the clamps folded into them).  The two inputs are
-// converted rounding toward zero, which saturates at the FP16 maximum 65504 instead of
-// overflowing.  Over every finite FP16 input the result stays within 1.2e-3 of Phi (checked
-// exhaustively on the GPU through dm_probe_gelu against the FP64 tanh form; the fit alone is
-// within 2.8e-4 on [-3, 3], and Phi(-3) = 1.3e-3 bounds the clamped tails), and the product
-// x Phi is rounded to FP16 once more.  Per pair of values that is 10 full-rate instructions;
-// the exact form's exp2 and reciprocal alone take four issue cycles each per value.
+// The tanh-form GELU on the quarter scale, u Phi(4u) for u = x / 4, Phi(x) = (1 + tanh(sqrt(2/pi)
+// (x + 0.044715 x^3))) / 2, in packed FP16 with no transcendental:
+//     Phi(4u) ~ clamp(1/2 + u P(u^2), 0, 1),  P(s) = p0 + p1 s + p2 s^2 + p3 s^3 + p4 s^4,
+// P a near-minimax fit of (Phi(4u) - 1/2) / u on |x| <= 3.2 (the interval chosen for the
+// smallest error after FP16 rounding).  Past it the odd polynomial u P(u^2) keeps growing
+// (p4 > 0) and the clamp takes the factor to exactly 0 or 1, where Phi is within 1.35e-3 of it;
+// very large |u| overflow u^2 to +inf, P to +inf and 1/2 + u P to +-inf, which the clamp also
+// maps to 0 or 1 (no inf - inf arises).  Each step is one packed FP16 instruction for two
+// values (the multiply-adds rounded once, the clamp folded into the last one): with the input
+// conversion (rounding toward zero, which saturates at +-65504 instead of overflowing) and the
+// final product, 8 instructions per pair; the exact form's exp2 and reciprocal alone take four
+// issue cycles each per value.  Over every finite FP16 input the factor stays within 1.2e-3 of
+// Phi (dm_probe_gelu checks that on the GPU against the FP64 tanh form; the fit alone is within
+// 4.5e-4), and the product u Phi~ is rounded to FP16 once more.
+template <class V>
+__device__ __forceinline__ V gelu_quarter(V u) {
+    const V zero = (V)(_Float16)0.0f, one = (V)(_Float16)1.0f;
+    const V s = u * u;
+    V p = (V)(_Float16)4.2214898859682375f;
+    p = __builtin_elementwise_fma(p, s, (V)(_Float16)-8.968631397847826f);
+    p = __builtin_elementwise_fma(p, s, (V)(_Float16)7.967970552331977f);
+    p = __builtin_elementwise_fma(p, s, (V)(_Float16)-4.039456706367537f);
+    p = __builtin_elementwise_fma(p, s, (V)(_Float16)1.5892242612118852f);
+    const V ph = __builtin_elementwise_min(__builtin_elementwise_max(__builtin_elementwise_fma(u, p, (V)(_Float16)0.5f), zero), one);
+    return u * ph;
+}
+
+// a, b: quarter-scale pre-activations h / 4; returns GELU(h) / 4 of both.
 __device__ __forceinline__ f16x2 gelu2(float a, float b) {
-    const f16x2 x = __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(a, b));
-    const f16x2 zero = (f16x2)(_Float16)0.0f, one = (f16x2)(_Float16)1.0f;
-    const f16x2 v = __builtin_elementwise_min(
-        __builtin_elementwise_max(__builtin_elementwise_fma(x, (f16x2)(_Float16)(1.0f / 6.0f), (f16x2)(_Float16)0.5f), zero),
-        one);
-    const f16x2 u = __builtin_elementwise_fma(v, (f16x2)(_Float16)2.0f, (f16x2)(_Float16)-1.0f);
-    const f16x2 s = u * u;
-    f16x2 p = (f16x2)(_Float16)0.393552818f;
-    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)-1.356858143f);
-    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)1.999497139f);
-    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)-1.730723903f);
-    p = __builtin_elementwise_fma(p, s, (f16x2)(_Float16)1.193597265f);
-    const f16x2 ph = __builtin_elementwise_min(
-        __builtin_elementwise_max(__builtin_elementwise_fma(u, p, (f16x2)(_Float16)0.5f), zero), one);
-    return x * ph;
+    return gelu_quarter(__builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(a, b)));
+}
+
+// Two pairs as one four-wide vector: each step becomes two independent packed instructions
+// back to back, which keeps the VALU pipeline full without the scheduler's help.
+__device__ __forceinline__ void gelu4(const float* v, f16x2& g0, f16x2& g1) {
+    const f16x2 x0 = __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(v[0], v[1]));
+    const f16x2 x1 = __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(v[2], v[3]));
+    const f16x4 r = gelu_quarter(f16x4{x0[0], x0[1], x1[0], x1[1]});
+    g0 = f16x2{r[0], r[1]};
+    g1 = f16x2{r[2], r[3]};
 }
 
 // Fragment table from row-major (out x in) BF16 weights: W1t [256 x 32] (inputs 0..13 used),
 // W2t [256 x 256], W3t [32 x 256]; the FP32 layer-1 bias b1 becomes input columns 14 (hi) and
-// 15 (lo).  W1 stays BF16; W2 and W3 become FP16 operands, exactly for magnitudes in
-// [2^-14, 65504], to within 2^-25 below that, saturated at 65504 above it.  One thread per
-// fragment.
-__device__ __forceinline__ _Float16 to_f16_sat(__bf16 w) {
-    return (_Float16)fminf(fmaxf((float)w, -65504.0f), 65504.0f);
+// 15 (lo).  W1 and b1 are stored divided by 4 (W1 stays BF16), W3 multiplied by 4; W2 and 4 W3
+// become FP16 operands, exactly for magnitudes in [2^-14, 65504], to within 2^-25 below that,
+// saturated at 65504 above it.  One thread per fragment.
+__device__ __forceinline__ _Float16 to_f16_sat(float w) {
+    return (_Float16)fminf(fmaxf(w, -65504.0f), 65504.0f);
 }
 
 __global__ void pack_kernel(const __bf16* W1t, const __bf16* W2t, const __bf16* W3t, const float* b1, uint4* frag) {
@@ -92,24 +111,25 @@ __global__ void pack_kernel(const __bf16* W1t, const __bf16* W2t, const __bf16* 
     if (f < kW1Frags) {
         const int b = f / 64, l = f % 64;
         const int u = perm_unit(b, l % 32);
-        const __bf16 hi = (__bf16)b1[u];
-        const __bf16 lo = (__bf16)(b1[u] - (float)hi);
+        const float bq = 0.25f * b1[u];
+        const __bf16 hi = (__bf16)bq;
+        const __bf16 lo = (__bf16)(bq - (float)hi);
         for (int q = 0; q < 8; ++q) {
             const int k = 8 * (l / 32) + q;
-            v[q] = k == 14 ? hi : (k == 15 ? lo : W1t[u * 32 + k]);
+            v[q] = k == 14 ? hi : (k == 15 ? lo : (__bf16)(0.25f * (float)W1t[u * 32 + k]));
         }
     } else if (f < kW1Frags + kW2Frags) {
         const int g = f - kW1Frags;
         const int b = g / (16 * 64), t = (g / 64) % 16, l = g % 64;
         const int u = perm_unit(b, l % 32);
-        for (int q = 0; q < 8; ++q) w[q] = to_f16_sat(W2t[u * kH + 16 * t + 8 * (l / 32) + q]);
+        for (int q = 0; q < 8; ++q) w[q] = to_f16_sat((float)W2t[u * kH + 16 * t + 8 * (l / 32) + q]);
         frag[f] = *reinterpret_cast<const uint4*>(w);
         return;
     } else {
         const int g = f - kW1Frags - kW2Frags;
         const int t = g / 64, l = g % 64;
         const int o = l % 32;
-        for (int q = 0; q < 8; ++q) w[q] = to_f16_sat(W3t[o * kH + 16 * t + 8 * (l / 32) + q]);
+        for (int q = 0; q < 8; ++q) w[q] = to_f16_sat(4.0f * (float)W3t[o * kH + 16 * t + 8 * (l / 32) + q]);
         frag[f] = *reinterpret_cast<const uint4*>(w);
         return;
     }
@@ -125,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
     // b2 as [block][h][r]: unit 32b + 16(r/8) + 8h + (r%8); b3 as [h][r]: output 8(r/4) + 4h + (r%4)
     for (int i = tid; i < 8 * 2 * 16; i += kThreads) {
         const int b = i / 32, hh = (i / 16) % 2, r = i % 16;
-        lbias[i] = a.bias[kH + 32 * b + 16 * (r >> 3) + 8 * hh + (r & 7)];
+        lbias[i] = 0.25f * a.bias[kH + 32 * b + 16 * (r >> 3) + 8 * hh + (r & 7)];  // b2 / 4
     }
     for (int i = tid; i < 32; i += kThreads) {
         const int hh = i / 16, r = i % 16;
@@ -139,7 +159,25 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
     const int64_t tiles = (a.N + 31) / 32;
     const int slot = (blockIdx.x * (kThreads / 64) + wave) % kAccSlots;
     double gsum = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave; t < tiles; t += (int64_t)gridDim.x * (kThreads / 64)) {
+    const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
+    // A tile's received values and transmitted rows are loaded one tile ahead, so their memory
+    // latency overlaps the previous tile's layers.
+    // The loads are unconditional (indices clamped into the arrays, N >= 1 here) and their
+    // values are masked only where they are used, a tile later: a load under a branch, or
+    // selected right away, would make the compiler wait for it at once.
+    float yv[8];
+    uint32_t txr = 0;
+    bool yact = false;
+    auto fetch = [&](int64_t tt) {
+        const int64_t nn = tt * 32 + j;
+        yact = nn < a.N;  // false past the last tile too
+        const size_t nc = (size_t)(yact ? nn : a.N - 1);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) yv[q] = a.y[nc * a.D + min(8 * h + q, a.D - 1)];
+        if (a.tx) txr = a.tx[nc];
+    };
+    fetch((int64_t)blockIdx.x * (kThreads / 64) + wave);
+    for (int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave; t < tiles; t += stride) {
         const int64_t n = t * 32 + j;
         const bool active = n < a.N;
         // features: slot k = 8h + q; k < D: y, k == D: SNR feature, k = 14, 15: 1 (bias), else 0
@@ -148,31 +186,53 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
         for (int q = 0; q < 8; ++q) {
             const int k = 8 * h + q;
             float v = 0.0f;
-            if (k < a.D) v = active ? a.y[(size_t)n * a.D + k] : 0.0f;
+            if (k < a.D) v = yact ? yv[q] : 0.0f;
             else if (k == a.D) v = a.snr_feature;
             else if (k >= 14) v = 1.0f;
             xf[q] = (__bf16)v;
         }
-        f16x8 a1[16];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, w1[b * 64 + lane]), xf, f32x16{}, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 16; r += 2) {
-                const f16x2 g2 = gelu2(acc[r], acc[r + 1]);
-                a1[2 * b + (r >> 3)][r & 7] = g2[0];
-                a1[2 * b + (r >> 3)][(r & 7) + 1] = g2[1];
-            }
+        uint32_t row_cur = yact ? txr : 0u;
+        {
+            // the values above are consumed before the next loads issue (the empty asm keeps
+            // the selects from sinking below them): a wait the compiler places for the values
+            // must not also cover those loads
+            uint4 xb = __builtin_bit_cast(uint4, xf);
+            asm volatile("" : "+v"(xb.x), "+v"(xb.y), "+v"(xb.z), "+v"(xb.w), "+v"(row_cur)::"memory");
+            xf = __builtin_bit_cast(bf16x8, xb);
         }
+        // label of the transmitted point, read now and used after layer 3
+        int txl = 0;
+        if (a.tx) {
+            uint32_t row = row_cur;
+            if (row >= (uint32_t)a.M) {
+                if (a.bad_tx) atomicOr(a.bad_tx, 1u);
+                row = 0;
+            }
+            txl = a.row2label[row];
+        }
+        fetch(t + stride);
+        // Two GELU pairs (two independent chains the scheduler interleaves) pinned where they
+        // are written: without the empty asm the compiler sinks them to their first use and the
+        // VALU work bunches up behind the MFMAs.
+        auto gelu4_here = [&](const float* v, f16x2& g0, f16x2& g1) {
+            gelu4(v, g0, g1);
+            uint32_t b0 = __builtin_bit_cast(uint32_t, g0);
+            uint32_t b1 = __builtin_bit_cast(uint32_t, g1);
+            asm volatile("" : "+v"(b0), "+v"(b1));
+            g0 = __builtin_bit_cast(f16x2, b0);
+            g1 = __builtin_bit_cast(f16x2, b1);
+        };
+        f16x8 a1[16];
         f32x16 acc3 = {};
         // Layer-2 weight fragments stream through a ring of kRing registers: the read of
         // fragment g + kRing is issued right after fragment g is consumed, so LDS latency
         // overlaps kRing - 1 MFMAs (the ring runs on across blocks; past the end it rereads the
         // last fragment, which is never used).  The layer is software-pipelined over its 8 output
         // blocks: while the 16 MFMAs of block b run, the wave evaluates block b-1's 16 GELUs, one
-        // per MFMA, and feeds them to layer 3 afterwards, so matrix and vector work overlap
-        // within the wave.
+        // pair per two MFMAs, and feeds them to layer 3 afterwards, so matrix and vector work
+        // overlap within the wave.  Layer 1 is folded into layer 2's first block the same way:
+        // layer-1 block b + 1's MFMA is issued before block b's GELUs, and layer-2 k-steps 2b and
+        // 2b + 1 run as soon as those GELUs have produced their operands.
         f16x8 ring[kRing];
 #pragma unroll
         for (int q = 0; q < kRing; ++q) ring[q] = __builtin_bit_cast(f16x8, w2[q * 64 + lane]);
@@ -196,11 +256,33 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
             }
             return acc;
         };
+        auto l1_mfma = [&](int b) {
+            return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, w1[b * 64 + lane]), xf,
+                                                           f32x16{}, 0, 0, 0);
+        };
         f32x16 accp = bias_acc(0);
+        f32x16 acc1 = l1_mfma(0);
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            accp = l2_step(0, ks, accp);
-            __builtin_amdgcn_sched_barrier(0);  // keep the read kRing steps ahead of its use
+        for (int b = 0; b < 8; ++b) {
+            f32x16 acc1n = {};
+            if (b < 7) acc1n = l1_mfma(b + 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+#pragma unroll
+                for (int r = 8 * half; r < 8 * half + 8; r += 4) {
+                    const float v[4] = {acc1[r], acc1[r + 1], acc1[r + 2], acc1[r + 3]};
+                    f16x2 g0, g1;
+                    gelu4_here(v, g0, g1);
+                    a1[2 * b + half][r & 7] = g0[0];
+                    a1[2 * b + half][(r & 7) + 1] = g0[1];
+                    a1[2 * b + half][(r & 7) + 2] = g1[0];
+                    a1[2 * b + half][(r & 7) + 3] = g1[1];
+                }
+                accp = l2_step(0, 2 * b + half, accp);
+                __builtin_amdgcn_sched_barrier(0);  // keep the read kRing steps ahead of its use
+            }
+            acc1 = acc1n;
         }
         // block p's GELUs feed layer 3; with `next` the MFMAs of block p + 1 run in between
         auto finish = [&](int p, bool next, f32x16& accn) {
@@ -210,21 +292,28 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks) {
                 if (next) accn = l2_step(p + 1, ks, accn);
-                if (ks & 1) {
-                    const f16x2 g2 = gelu2(accp[ks - 1], accp[ks]);
-                    if (ks < 8) {
-                        lo[ks - 1] = g2[0];
-                        lo[ks] = g2[1];
+                if ((ks & 3) == 3) {
+                    const float v[4] = {accp[ks - 3], accp[ks - 2], accp[ks - 1], accp[ks]};
+                    f16x2 g0, g1;
+                    if (next) {
+                        gelu4_here(v, g0, g1);
                     } else {
-                        hi[ks - 9] = g2[0];
-                        hi[ks - 8] = g2[1];
+                        gelu4(v, g0, g1);
                     }
+                    f16x8& dst = ks < 8 ? lo : hi;
+                    dst[(ks & 7) - 3] = g0[0];
+                    dst[(ks & 7) - 2] = g0[1];
+                    dst[(ks & 7) - 1] = g1[0];
+                    dst[ks & 7] = g1[1];
                 }
+                // one MFMA and its ring read per step, two GELU pairs every fourth step: the read
+                // stays kRing steps ahead of its use and the GELUs spread over the MFMAs
+                if (next) __builtin_amdgcn_sched_barrier(0);
             }
             acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w3lo, lo, acc3, 0, 0, 0);
             acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w3hi, hi, acc3, 0, 0, 0);
         };
-#pragma unroll 1
+#pragma unroll
         for (int b = 1; b < 8; ++b) {
             f32x16 accn = bias_acc(b);
             finish(b - 1, true, accn);
@@ -235,15 +324,6 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
             finish(7, false, unused);
         }
         // outputs: register r holds output o = 8 (r / 4) + 4 h + (r % 4) of symbol n
-        int txl = 0;
-        if (a.tx && active) {
-            uint32_t row = a.tx[n];
-            if (row >= (uint32_t)a.M) {
-                if (a.bad_tx) atomicOr(a.bad_tx, 1u);
-                row = 0;
-            }
-            txl = a.row2label[row];
-        }
         const float* b3 = lbias + 8 * 2 * 16 + h * 16;
         float g = 0.0f;
 #pragma unroll
@@ -255,17 +335,20 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
                 g += gmi_bit_term(lam * 1.4426950408889634f, (txl >> (a.m - 1 - o)) & 1);
             }
         }
-        if (a.acc) gsum += wave_sum(active ? (double)g : 0.0);
+        gsum += active ? (double)g : 0.0;
     }
-    if (a.acc && lane == 0) acc_add(a.acc, 0, slot, 0, gsum);
+    if (a.acc) {
+        gsum = wave_sum(gsum);
+        if (lane == 0) acc_add(a.acc, 0, slot, 0, gsum);
+    }
 }
 
 __global__ void probe_gelu_kernel(const float* x, float* out, int64_t n) {
     const int64_t i = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
-    const f16x2 g = gelu2(x[i], i + 1 < n ? x[i + 1] : 0.0f);
-    out[i] = (float)g[0];
-    if (i + 1 < n) out[i + 1] = (float)g[1];
+    const f16x2 g = gelu2(0.25f * x[i], i + 1 < n ? 0.25f * x[i + 1] : 0.0f);
+    out[i] = 4.0f * (float)g[0];
+    if (i + 1 < n) out[i + 1] = 4.0f * (float)g[1];
 }
 
 }  // namespace
