@@ -313,12 +313,17 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
             acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w3lo, lo, acc3, 0, 0, 0);
             acc3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w3hi, hi, acc3, 0, 0, 0);
         };
+        // Waves w and w + 4 share a SIMD.  During the MFMA-bound blocks a raised wave priority
+        // lets this wave's matrix instructions issue ahead of the other wave's vector work, which
+        // then fills the gaps (measured: +2% over equal priorities).
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int b = 1; b < 8; ++b) {
             f32x16 accn = bias_acc(b);
             finish(b - 1, true, accn);
             accp = accn;
         }
+        __builtin_amdgcn_s_setprio(0);
         {
             f32x16 unused = {};
             finish(7, false, unused);
