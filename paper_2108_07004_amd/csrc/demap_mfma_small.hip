@@ -1,10 +1,15 @@
 // Exact soft demapper for constellations of 32 to 256 points (one to eight 32-point tiles) with
 // the distance cross term on MFMA (gfx950): the multi-SNR launch over one constellation with the
 // tile count fixed at compile time (tile loop and subset sums in mfma_small.hpp, epilogue in
-// mfma_body.hpp).  The whole operand table (at most 8 tiles x 2 MFMAs x 1 KiB), the per-label
-// operand rows of the MI term (at most 16 KiB) and the row-to-label map are staged in LDS once
-// per block, so that the transmitted label and its operand row, read once per batch, cost LDS
-// rather than global-memory latency.
+// mfma_body.hpp).  The whole operand table (at most 8 tiles x 2 MFMAs x 1 KiB), the FP32 points
+// (at most 8 KiB) and the row-to-label map are staged in LDS once per block, so that the
+// transmitted label and its point, read once per batch, cost LDS rather than global-memory
+// latency.  With split FP16 operands the MI term takes the transmitted point's exponent from the
+// direct FP32 differences (a few VALU instructions) instead of a diagonal MFMA product and a
+// register select; the other precisions keep the diagonal product (their per-label operand
+// rows are staged too).
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "mfma_body.hpp"
@@ -23,7 +28,10 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
     constexpr int S = Slots<D, SPLIT>::S;
     constexpr int MB = SmallBits<NT>::MB;  // label bits of the constellation
     __shared__ uint4 lds_frag[NT * S * 64];     // [tile][s][lane] x 16 bytes
-    __shared__ uint4 lds_pv[NT * 32 * 2 * S];   // [label][16 S halves]
+    __shared__ float lds_tab[NT * 32 * D];      // FP32 points in label order
+    // the transmitted point's MI exponent from FP32 differences only with split FP16 operands
+    constexpr bool kDirectTx = SPLIT && std::is_same<T, _Float16>::value;
+    __shared__ uint4 lds_pv[kDirectTx ? 1 : NT * 32 * 2 * S];  // [label][16 S halves]
     __shared__ uint16_t lds_r2l[NT * 32];       // row -> label
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -32,7 +40,9 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
     const int wave_slot = (blockIdx.x * kWaves + wave) % kAccSlots;
     const Sinks& k = a.sinks;
     for (int i = tid; i < NT * S * 64; i += kThreads) lds_frag[i] = frag[i];
-    for (int i = tid; i < NT * 32 * 2 * S; i += kThreads) lds_pv[i] = reinterpret_cast<const uint4*>(pv)[i];
+    for (int i = tid; i < NT * 32 * D; i += kThreads) lds_tab[i] = a.table[i];
+    if constexpr (!kDirectTx)
+        for (int i = tid; i < NT * 32 * 2 * S; i += kThreads) lds_pv[i] = reinterpret_cast<const uint4*>(pv)[i];
     for (int i = tid; i < NT * 32; i += kThreads) lds_r2l[i] = a.row2label[i];
     __syncthreads();
 
@@ -97,10 +107,17 @@ __global__ __launch_bounds__(kThreads) void demap_mfma_small_kernel(const Launch
 
         float S0[MB], S1[MB], tot;
         mfma_small_sums<T, D, SPLIT, NT>(lds_frag, lane, bfr, S0, S1, tot);
+        // The MI term's exponent of the transmitted point: with split FP16 operands from the
+        // direct FP32 differences (the MFMA exponents carry ~1e-6 of rounding, which then stays
+        // in the MI term instead of cancelling); with the coarser BF16 split and the plain
+        // operands from the same MFMA arithmetic as the sum, so that the transmitted point's own
+        // rounding cancels (with BF16 splits the direct form was 1.2e-4 bit off in MI on
+        // DP-16QAM at high SNR).
+        const float ttx = fmaf(-b.c, sqdist<D>(y, lds_tab + txl * D), b.K);
         float g, mi;
         uint32_t mask, near;
         mfma_finish<T, D, SPLIT, MB>(b, k, reinterpret_cast<const uint16_t*>(lds_pv), bfr, S0, S1, tot, n, active, bad,
-                                     txl, lane, g, mi, &mask, &near);
+                                     txl, lane, g, mi, &mask, &near, kDirectTx ? &ttx : nullptr);
         // far subsets of flagged bits resolved in the wave (at high SNR nearly every batch has
         // some; each would otherwise be a queue entry and a recomputation from the queue)
         mfma_small_far_pass<T, D, SPLIT, NT>(lds_frag, lane, y, b.c, b.K, bad, b, n, active, txl, near, mask, g);

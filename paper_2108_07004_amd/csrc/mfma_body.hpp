@@ -311,7 +311,7 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
                                             const Frags<T, Slots<D, SPLIT>::S>& bfr, const float (&S0)[MB],
                                             const float (&S1)[MB], float tot, int64_t n, bool active, bool bad,
                                             int txl, int lane, float& g, float& mi, uint32_t* defer = nullptr,
-                                            uint32_t* defer_near = nullptr) {
+                                            uint32_t* defer_near = nullptr, const float* ttx_direct = nullptr) {
     using V = typename Mma<T>::V;
     constexpr int S = Slots<D, SPLIT>::S;
     constexpr int NJ = (MB + 1) / 2;
@@ -396,7 +396,20 @@ __device__ __forceinline__ void mfma_finish(const BlockView& b, const Sinks& k, 
     // l%32 with the point-side vector of its own symbol's transmitted label; the diagonal
     // element (l%32, l%32) sits in register 4*(j>>3) + (j&3) of the lane half (j>>2)&1.
     mi = 0.0f;
-    if (b.tx) {
+    if (b.tx && ttx_direct) {
+        // the caller's FP32 exponent of the transmitted point, K - c ||y - x_tx||^2 from the
+        // direct differences: it differs from that point's MFMA exponent inside stot by the
+        // operands' rounding (~1e-5 in log2 units for the split precisions), not by a bias
+        if (h == 0) {
+            if (!bad_sym && stot >= b.flag_thresh && stot < 3.0e38f) {
+                const int e = __builtin_amdgcn_frexp_expf(stot);
+                const float mant = __builtin_amdgcn_frexp_mantf(stot);
+                mi = ((float)(m - e) + *ttx_direct) - hw_log2(mant);
+            } else {
+                mask |= kMiFlag;
+            }
+        }
+    } else if (b.tx) {
         const uint16_t* pr = pv + (size_t)txl * (16 * S) + 8 * h;
         f32x16 dg = Mma<T>::run(__builtin_bit_cast(V, *(const uint4*)pr), bfr.v[0]);
 #pragma unroll

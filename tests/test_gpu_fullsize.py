@@ -202,7 +202,12 @@ def test_benchmark_plan_matches_single_instance_path_and_sampled_oracle():
         c, s2, y_t, tx_t, llr = items[i]
         prec = "fp32" if kinds[i] == 0 else "fp16x3"
         g1, m1 = dm.gmi_estimate(c, [s2], [y_t], tx_t, None, prec=prec)
-        assert abs(gmi[i] - g1[0]) <= 1e-6 and abs(mi[i] - m1[0]) <= 1e-6, (i, gmi[i], g1[0], mi[i], m1[0])
+        # Same arithmetic for the GMI.  For the MI term the single-constellation kernel of
+        # 32..256 points takes the transmitted point's exponent from FP32 differences, the
+        # batched kernel from its split-FP16 MFMA product: per symbol they differ by that
+        # product's rounding (~1e-5 in log2 units at most, averaging out over the block).
+        mi_tol = 1e-6 if kinds[i] == 0 else 1e-5
+        assert abs(gmi[i] - g1[0]) <= 1e-6 and abs(mi[i] - m1[0]) <= mi_tol, (i, gmi[i], g1[0], mi[i], m1[0])
         idx = np.unique(g.integers(0, inst.N, 64))
         y = y_t[idx].cpu().numpy()
         ref = oracle.demap(inst.const.points, inst.const.labels, s2, y, tx[idx])
