@@ -109,11 +109,13 @@ __device__ __forceinline__ void mfma_small_sums(const uint4* lds_frag, int lane,
 // far side, the same exponent arithmetic as every other LLR of the precision; the LLR is
 // written, its GMI term added to g and the bit cleared from mask.  A far sum under 2^-95 (where
 // flushed terms could matter) leaves its bit in mask for the fix-up queue, as do symbols
-// without the near log-sum and the MI term.
+// without the near log-sum and the MI term.  When the pass has tried every flagged bit of a
+// symbol, near is set to kNearNone: the bits left would fail the fix-up's far-only sum the same
+// way (same shift, same bound), so the fix-up takes their two-pass sums at once.
 template <typename T, int D, bool SPLIT, int NT>
 __device__ __forceinline__ void mfma_small_far_pass(const uint4* lds_frag, int lane, const float (&y)[D], float c,
                                                     float K, bool bad, const BlockView& b, int64_t n, bool active,
-                                                    int txl, uint32_t near, uint32_t& mask, float& g) {
+                                                    int txl, uint32_t& near, uint32_t& mask, float& g) {
     constexpr int MB = SmallBits<NT>::MB;
     constexpr int S = Slots<D, SPLIT>::S;
     constexpr float sh = (float)(MB - 102);
@@ -147,6 +149,7 @@ __device__ __forceinline__ void mfma_small_far_pass(const uint4* lds_frag, int l
         }
     }
     mask &= ~half_or(done);
+    if (far != 0u && !bad_sym) near = kNearNone;
 }
 
 }  // namespace dm
