@@ -152,11 +152,12 @@ __device__ __forceinline__ float row_reduce_f(float v, Op op) {
 // corrections, which add(tag, slot, which, value) receives.
 //
 // A wave's four rows run the bit loop for the union of their flagged bits, so the queue is taken
-// in chunks of 256 entries per workgroup (256 threads), each chunk counting-sorted by the low
-// eight mask bits in LDS before its rows are dealt out: rows of a wave then mostly share their
-// flagged bits.  The processing order does not change any result (each (symbol, bit) is written
+// in chunks of 512 entries per workgroup (256 threads, two entries each), each chunk
+// counting-sorted by the low eight mask bits in LDS before its rows are dealt out: rows of a wave
+// then mostly share their flagged bits.  The processing order does not change any result (each (symbol, bit) is written
 // once, the corrections are integer sums).
-constexpr int kFixSortChunk = 256;
+constexpr int kFixSortChunk = 256;  // threads per workgroup and sort bins (low eight mask bits)
+constexpr int kFixRowChunk = 512;   // entries per chunk: two per thread, so more rows share a mask
 
 template <int DP, int NPL, typename ViewFn, typename AddFn, typename FetchFn, typename CountFn>
 __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, CountFn count_pairs, uint32_t count,
@@ -173,7 +174,7 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
         __syncthreads();
         tab = s_tab;
     }
-    __shared__ FixEntry s_sorted[kFixSortChunk];
+    __shared__ FixEntry s_sorted[kFixRowChunk];
     __shared__ uint32_t s_bin[256];
     __shared__ uint32_t s_wsum[kFixSortChunk / 64];
     const int tid = threadIdx.x;  // blockDim.x == kFixSortChunk
@@ -184,22 +185,30 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
     const int slot = (int)(wave % kAccSlots);
     const auto fmax2 = [](float a, float b) { return fmaxf(a, b); };
     const auto fadd2 = [](float a, float b) { return a + b; };
-    for (uint32_t c0 = blockIdx.x * kFixSortChunk; c0 < count; c0 += gridDim.x * kFixSortChunk) {  // uniform per block
-        const uint32_t nc = min((uint32_t)kFixSortChunk, count - c0);
+    constexpr int kPer = kFixRowChunk / kFixSortChunk;
+    for (uint32_t c0 = blockIdx.x * kFixRowChunk; c0 < count; c0 += gridDim.x * kFixRowChunk) {  // uniform per block
+        const uint32_t nc = min((uint32_t)kFixRowChunk, count - c0);
         // counting sort of the chunk by key = low 8 mask bits
         s_bin[tid] = 0u;
         __syncthreads();
-        FixEntry mine{};
-        uint32_t key = 0u;
-        bool have = false;  // an entry with bits left to recompute
-        if ((uint32_t)tid < nc) {
-            mine = fetch(c0 + tid);
-            count_pairs(mine);
-            have = (mine.mask & (0xFFFFu | kMiFlag)) != 0u;
-        }
-        if (have) {
-            key = mine.mask & 0xFFu;
-            atomicAdd(&s_bin[key], 1u);
+        FixEntry mine[kPer];
+        uint32_t key[kPer];
+        bool have[kPer];  // an entry with bits left to recompute
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const uint32_t idx = (uint32_t)(tid + q * kFixSortChunk);
+            mine[q] = FixEntry{};
+            key[q] = 0u;
+            have[q] = false;
+            if (idx < nc) {
+                mine[q] = fetch(c0 + idx);
+                count_pairs(mine[q]);
+                have[q] = (mine[q].mask & (0xFFFFu | kMiFlag)) != 0u;
+            }
+            if (have[q]) {
+                key[q] = mine[q].mask & 0xFFu;
+                atomicAdd(&s_bin[key[q]], 1u);
+            }
         }
         __syncthreads();
         const uint32_t own = s_bin[tid];
@@ -218,7 +227,9 @@ __device__ void fix_rows(const Sinks& k, ViewFn view, AddFn add, FetchFn fetch, 
         }
         s_bin[tid] = x + pre - own;  // exclusive start of bin tid
         __syncthreads();
-        if (have) s_sorted[atomicAdd(&s_bin[key], 1u)] = mine;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (have[q]) s_sorted[atomicAdd(&s_bin[key[q]], 1u)] = mine[q];
         __syncthreads();
         for (uint32_t base = (uint32_t)wv * 4; base < nl; base += (blockDim.x >> 6) * 4) {  // uniform over the wave
             const uint32_t i = base + (uint32_t)(lane >> 4);
