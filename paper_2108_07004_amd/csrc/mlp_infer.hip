@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kThreads) void mlp_infer_kernel(const MlpInferArgs 
     const uint4* w2 = lds + kW1Frags;
     const uint4* w3 = lds + kW1Frags + kW2Frags;
 
+    if (a.N <= 0) return;  // the clamped loads below need a row 0 (callers skip empty ranges)
     const int64_t tiles = (a.N + 31) / 32;
     const int slot = (blockIdx.x * (kThreads / 64) + wave) % kAccSlots;
     double gsum = 0.0;
