@@ -41,10 +41,10 @@ EXP2_ISSUE_CYCLES = 2  # v_exp_f32 issues at half the full FP32 rate on gfx950 (
 # 512 MiB device copy in the same runs.  Valid only for the kernel sources they were taken on.
 TRAFFIC_PMC = {
     "prec": "fp16x3", "workload": "gauss8d2048",
-    "bytes": (4558300 * 2 + 11553696) * 1024,
+    "bytes": (4557756 * 2 + 11553688) * 1024,
     "sources": ["paper_2108_07004_amd/csrc/demap_mfma.hip", "paper_2108_07004_amd/csrc/mfma_body.hpp",
                 "paper_2108_07004_amd/csrc/device_common.hpp"],
-    "sha256": "657e13a5808c5488174927c828908713fcdf13def68f79ca15d10f4eddbcbc87",
+    "sha256": "da3faffe0363e2186425b0a0a2c6164d593fc7a6daae0e3a7a06c253458be345",
 }
 
 
