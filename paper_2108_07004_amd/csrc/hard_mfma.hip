@@ -4,10 +4,11 @@
 // point u~ = K + 2 y.x - ||x||^2 - ||y||^2 = K - ||y - x||^2, with a per-symbol offset
 // K = (||y|| + r_max)^2 + 1 that keeps every u~ positive, so the bit patterns of the u~ order
 // like their values.  Register r of tile t holds label 32 t + 16 h + r; each lane keeps, per
-// register slot r, the largest value with the (complemented) tile index written into its low
-// 7 mantissa bits, and one running maximum of everything that lost a comparison (the overall
-// runner-up once combined with the slots): four vector instructions per (symbol, point), all
-// unsigned integer max / min.  Per value, |u~ - u| is at most 3.5e-6 K (FP32 accumulation of
+// register slot r, the largest and second-largest values with the (complemented) tile index
+// written into their low 7 mantissa bits.  Tiles are taken in pairs: with a, b the slot's two
+// new values, best = max3(best, a, b) and second = max(second, med3(best, a, b)) (the second
+// largest of {best, second, a, b}, as second <= best): with the field inserts, five vector
+// instructions per two (symbol, point) pairs, all unsigned integer max / med3 / bit operations.  Per value, |u~ - u| is at most 3.5e-6 K (FP32 accumulation of
 // 3D + 5 terms bounded by 2K) + 1e-6 K (operand splitting, dropped lo*lo products) + 5.4e-7 K
 // (rounding of the reference FP32 distance) + 7.6e-6 K (the 7 packed bits), under 1.3e-5 K in
 // all; with eps = 2^-14 K (+ a floor for FP16 subnormal lo parts) a gap best - second > 2 eps
@@ -114,10 +115,10 @@ __global__ __launch_bounds__(kHardMfmaThreads) void hard_mfma_kernel(const HardA
         const float K = fmaf(rr, rr, 1.0f);
         bool bad = false;
         const Frags<T, S> bfr = build_symbol_frags<T, D, true>(y, 1.0f, K, h, bad);
-        // per register slot r: largest packed u~ (field = kTileMask - t); sec: largest loser
-        uint32_t best[16], sec = 0u;
+        // per register slot r: largest and second-largest packed u~ (field = kTileMask - t)
+        uint32_t best[16], sec[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) best[r] = 0u;
+        for (int r = 0; r < 16; ++r) best[r] = sec[r] = 0u;
         // the mask lives in a register so that masking and inserting the (scalar) tile field is
         // one v_and_or_b32 (a literal mask and a scalar field would need two instructions)
         uint32_t keep = ~kTileMask;
@@ -137,37 +138,43 @@ __global__ __launch_bounds__(kHardMfmaThreads) void hard_mfma_kernel(const HardA
                 for (int q = 1; q < S; ++q) acc = Mma<T>::run(__builtin_bit_cast(V, fp[q * 64]), bfr.v[q], acc);
                 return acc;
             };
-            auto consume = [&](const f32x16& acc, int t) {
-                const uint32_t field = kTileMask - (uint32_t)(t0 + t);
+            // Tiles t and t + 1 together.  Their MFMAs are not issued ahead of the previous pair's
+            // ranking: two more accumulators would spill, and the other waves of the SIMD cover
+            // the MFMA latency.
+            for (int t = 0; t + 1 < cnt; t += 2) {
+                const f32x16 xa = tile_mma(t), xb = tile_mma(t + 1);
+                const uint32_t fa = kTileMask - (uint32_t)(t0 + t), fb = fa - 1u;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const uint32_t e = (__float_as_uint(acc[r]) & keep) | field;
-                    sec = max(sec, min(best[r], e));
-                    best[r] = max(best[r], e);
+                    const uint32_t a = (__float_as_uint(xa[r]) & keep) | fa;
+                    const uint32_t b = (__float_as_uint(xb[r]) & keep) | fb;
+                    uint32_t med;  // median of three (the compiler's own pattern match misses it here)
+                    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(med) : "v"(best[r]), "v"(a), "v"(b));
+                    sec[r] = max(sec[r], med);
+                    best[r] = max(max(best[r], a), b);
                 }
-            };
-            // the MFMAs of tile t+1 are issued before tile t is consumed (alternating accumulators)
-            const int last = cnt - 1;
-            f32x16 acc0 = tile_mma(0), acc1;
-            for (int t = 0; t < cnt; t += 2) {
-                acc1 = tile_mma(min(t + 1, last));
-                consume(acc0, t);
-                if (t + 1 < cnt) {
-                    acc0 = tile_mma(min(t + 2, last));
-                    consume(acc1, t + 1);
+            }
+            if (cnt & 1) {  // the last tile of an odd count alone
+                const f32x16 xa = tile_mma(cnt - 1);
+                const uint32_t fa = kTileMask - (uint32_t)(t0 + cnt - 1);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t a = (__float_as_uint(xa[r]) & keep) | fa;
+                    sec[r] = max(sec[r], min(best[r], a));
+                    best[r] = max(best[r], a);
                 }
             }
         }
         // this half's winner (slot r1) and runner-up, then the two halves of the symbol
-        uint32_t b1 = best[0], b2 = 0u;
+        uint32_t b1 = best[0], b2 = sec[0];
         int r1 = 0;
 #pragma unroll
         for (int r = 1; r < 16; ++r) {
-            b2 = max(b2, min(b1, best[r]));
+            b2 = max(max(b2, sec[r]), min(b1, best[r]));
             r1 = best[r] > b1 ? r : r1;
             b1 = max(b1, best[r]);
         }
-        const uint32_t s1 = max(sec, b2);
+        const uint32_t s1 = b2;
         const uint32_t pb = __shfl_xor(b1, 32, 64), ps = __shfl_xor(s1, 32, 64);
         const int pr = __shfl_xor(r1, 32, 64);
         const bool pbad = __shfl_xor((int)bad, 32, 64);
